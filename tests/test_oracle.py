@@ -1,0 +1,261 @@
+"""Pins for the CPU oracle (CPU only).
+
+Each test fixes part of the oracle against something other than the oracle itself:
+hand-worked fixtures, brute-force path enumeration, closed forms, a third-party BFS and
+betweenness implementation, and the exact uint64 overflow boundary.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_1409_7764_amd import graphgen as gg
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def rel_close(x, y, tol):
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    zero = y == 0
+    assert np.all(x[zero] == 0), "structural zero not exact"
+    nz = ~zero
+    err = np.abs(x[nz] - y[nz]) / np.abs(y[nz])
+    assert err.size == 0 or err.max() <= tol, f"max rel err {err.max()}"
+
+
+def read_fixture(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *vals = line.split()
+            out[key] = vals
+    return out
+
+
+def frac(s):
+    return Fraction(s)
+
+
+# --------------------------------------------------------------------------------------
+# hand-worked fixtures (definition of section I)
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["diamond.txt", "path_with_tail.txt", "three_branch.txt"])
+def test_golden_hand_worked(orc, name):
+    fx = read_fixture(name)
+    n = int(fx["n"][0])
+    e = np.array(fx["edges"], dtype=np.int64).reshape(-1, 2)
+    g = orc.Graph(n, e[:, 0], e[:, 1])
+    bc, _, _ = orc.bc(g)
+    want = np.array([float(frac(x)) for x in fx["bc"]])
+    rel_close(bc, want, 1e-15)
+    r = orc.brandes_source(g, 0)
+    assert r["dist"].tolist() == [int(x) for x in fx["dist0"]]
+    assert r["sigma"].tolist() == [int(x) for x in fx["sigma0"]]
+    rel_close(r["delta"], [float(frac(x)) for x in fx["delta0"]], 1e-15)
+
+
+def test_golden_ba_edge_count():
+    fx = read_fixture("ba_5000_5.txt")
+    n, beta, m = int(fx["n"][0]), int(fx["beta"][0]), int(fx["m"][0])
+    nn, u, v = gg.barabasi_albert(n, beta, seed=3)
+    pairs = set(zip(u.tolist(), v.tolist()))
+    assert nn == n and len(u) == m and len(pairs) == m
+    assert all((b, a) in pairs for a, b in pairs)          # symmetric digraph
+
+
+# --------------------------------------------------------------------------------------
+# brute force on tiny random digraphs (loops and duplicates included in the input)
+# --------------------------------------------------------------------------------------
+def test_brute_force_random_small(orc):
+    from oracle.brute import brute_force
+    rng = np.random.default_rng(1234)
+    for trial in range(250):
+        n = int(rng.integers(1, 8))
+        m = int(rng.integers(0, 3 * n + 1))
+        u = rng.integers(0, n, size=m)
+        v = rng.integers(0, n, size=m)
+        dist, sigma, bcx = brute_force(n, u, v)
+        g = orc.Graph(n, u, v)
+        bc, ovf, _ = orc.bc(g, threads=2)
+        assert not ovf.any()
+        rel_close(bc, [float(x) for x in bcx], 1e-12)
+        for s in range(n):
+            r = orc.brandes_source(g, s)
+            assert r["dist"].tolist() == dist[s], (trial, s)
+            assert r["sigma"].tolist() == sigma[s], (trial, s)
+
+
+# --------------------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 3, 7, 40])
+def test_directed_path(orc, n):
+    g = orc.Graph(*gg.directed_path(n))
+    bc, _, _ = orc.bc(g)
+    assert bc.tolist() == [float(i * (n - 1 - i)) for i in range(n)]
+    r = orc.brandes_source(g, 0)
+    assert r["dist"].tolist() == list(range(n))
+    assert r["sigma"].tolist() == [1] * n
+
+
+@pytest.mark.parametrize("n", [3, 9, 50])
+def test_stars(orc, n):
+    bc, _, _ = orc.bc(orc.Graph(*gg.bidirectional_star(n, centre=n // 2)))
+    want = np.zeros(n)
+    want[n // 2] = (n - 1) * (n - 2)
+    assert bc.tolist() == want.tolist()
+    nn, u, v = gg.out_star(n)
+    assert orc.bc(orc.Graph(nn, u, v))[0].tolist() == [0.0] * n
+    assert orc.bc(orc.Graph(nn, v, u))[0].tolist() == [0.0] * n          # in-star
+
+
+@pytest.mark.parametrize("n", [2, 5, 33])
+def test_directed_cycle(orc, n):
+    bc, _, _ = orc.bc(orc.Graph(*gg.directed_cycle(n)))
+    assert bc.tolist() == [float((n - 1) * (n - 2) // 2)] * n
+
+
+def test_complete_digraph(orc):
+    n = 12
+    g = orc.Graph(*gg.complete_digraph(n))
+    assert orc.bc(g)[0].tolist() == [0.0] * n
+    r = orc.brandes_source(g, 5)
+    assert r["dist"].tolist() == [1] * 5 + [0] + [1] * 6
+    assert r["sigma"].tolist() == [1] * n
+
+
+def test_grid_dag_binomial_sigma(orc):
+    # sigma from the corner is C(i+j, i); C(67,33) < 2^64 <= C(68,34)
+    assert math.comb(67, 33) < 2**64 <= math.comb(68, 34)
+    g = orc.Graph(*gg.grid_dag(34, 34))
+    r = orc.brandes_source(g, 0)
+    assert not r["overflow"]
+    want = [math.comb(i + j, i) for i in range(34) for j in range(34)]
+    assert [int(x) for x in r["sigma"]] == want
+    assert r["dist"].tolist() == [i + j for i in range(34) for j in range(34)]
+    g = orc.Graph(*gg.grid_dag(35, 35))
+    r = orc.brandes_source(g, 0)
+    assert r["overflow"]
+    want = np.array([float(math.comb(i + j, i)) for i in range(35) for j in range(35)])
+    rel_close(r["sigma_f"], want, 1e-13)
+    # every other corner-free source of the 35x35 grid stays below the boundary
+    assert not orc.brandes_source(g, 1)["overflow"]
+
+
+@pytest.mark.parametrize("k,overflow", [(62, False), (63, False), (64, True), (70, True)])
+def test_diamond_chain_overflow_boundary(orc, k, overflow):
+    g = orc.Graph(*gg.diamond_chain(k))
+    r = orc.brandes_source(g, 0)
+    assert r["overflow"] == overflow
+    if not overflow:
+        assert int(r["sigma"][3 * k]) == 2**k
+    assert r["sigma_f"][3 * k] == float(2**k)
+    _, ovf, _ = orc.bc(g, sources=np.array([0, 1, 3], dtype=np.uint32))
+    # from a_0 (id 1) and from j_1 (id 3) the last joint has 2^(k-1) paths
+    assert ovf.tolist() == [int(overflow), int(k - 1 >= 64), int(k - 1 >= 64)]
+
+
+def test_diamond_chain_closed_form(orc):
+    # Joint j_i (0 < i < k) is a cut vertex between the 3i vertices before it and the
+    # 3(k-i) after it, and every such ordered pair reaches across: BC(j_i) = 9 i (k-i).
+    # A middle vertex of diamond i carries half of the paths from the 3i+1 vertices up
+    # to j_i to the 3(k-i)-2 vertices from j_{i+1} on: BC = (3i+1)(3(k-i)-2)/2.
+    k = 10
+    g = orc.Graph(*gg.diamond_chain(k))
+    bc, _, _ = orc.bc(g)
+    want = np.zeros(3 * k + 1)
+    for i in range(1, k):
+        want[3 * i] = 9 * i * (k - i)
+    for i in range(k):
+        want[3 * i + 1] = want[3 * i + 2] = (3 * i + 1) * (3 * (k - i) - 2) / 2
+    assert bc.tolist() == want.tolist()
+
+
+# --------------------------------------------------------------------------------------
+# third-party cross-checks: scipy BFS distances, NetworkX betweenness (the paper's own
+# correctness check, section II-A)
+# --------------------------------------------------------------------------------------
+def _scipy_dist(n, row_ptr, col):
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    a = csr_matrix((np.ones(len(col)), col.astype(np.int64), row_ptr.astype(np.int64)), shape=(n, n))
+    return shortest_path(a, method="D", directed=True, unweighted=True)
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(7, 8, 1), (9, 4, 2)])
+def test_sum_invariant_vs_scipy(orc, scale, ef, seed):
+    # sum_v BC(v) = sum over reachable ordered pairs s != t of (d(s,t) - 1)
+    n, u, v = gg.rmat(scale, ef, seed)
+    g = orc.Graph(n, u, v)
+    bc, _, stats = orc.bc(g)
+    d = _scipy_dist(n, g.row_ptr, g.col)
+    fin = np.isfinite(d) & (d > 0)
+    want = float((d[fin] - 1).sum())
+    assert abs(bc.sum() - want) <= 1e-9 * want
+    # per source: delta_s(s) = |R_s| - 1, and sum over v != s of delta_s(v) = sum_t (d(s,t)-1)
+    for s in [0, 3, 17, 50]:
+        r = orc.brandes_source(g, s)
+        reach = int(np.isfinite(d[s]).sum())
+        assert r["reached"] == reach
+        assert abs(r["delta"][s] - (reach - 1)) <= 1e-12 * max(reach, 1)
+        others = r["delta"].sum() - r["delta"][s]
+        want_s = float((d[s][np.isfinite(d[s]) & (d[s] > 0)] - 1).sum())
+        assert abs(others - want_s) <= 1e-12 * max(want_s, 1)
+        dd = np.where(np.isfinite(d[s]), d[s], -1).astype(np.int64)
+        assert r["dist"].tolist() == dd.tolist()
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(8, 8, 10), (9, 8, 11)])
+def test_networkx_exact_and_subset(orc, scale, ef, seed):
+    nx = pytest.importorskip("networkx")
+    n, u, v = gg.rmat(scale, ef, seed)
+    g = orc.Graph(n, u, v)
+    G = nx.DiGraph()
+    G.add_nodes_from(range(n))
+    G.add_edges_from((int(a), int(b)) for a, b in zip(u, v) if a != b)
+    assert G.number_of_edges() == g.m
+    want = nx.betweenness_centrality(G, normalized=False)
+    bc, _, _ = orc.bc(g)
+    rel_close(bc, [want[i] for i in range(n)], 1e-9)
+    S = gg.uniform_sources(n, 40, seed=seed + 1)
+    want = nx.betweenness_centrality_subset(G, sources=[int(s) for s in S], targets=list(range(n)),
+                                            normalized=False)
+    bc, _, _ = orc.bc(g, sources=S)
+    rel_close(bc, [want[i] for i in range(n)], 1e-9)
+
+
+def test_adjacency_vs_numpy_unique(orc):
+    n, u, v = gg.rmat(10, 8, 10)
+    g = orc.Graph(n, u, v)
+    keep = u != v
+    pairs = np.unique(np.stack([u[keep], v[keep]], 1).astype(np.int64), axis=0)
+    assert g.m == pairs.shape[0]
+    assert np.array_equal(g.col, pairs[:, 1].astype(np.uint32))
+    assert np.array_equal(np.diff(g.row_ptr.astype(np.int64)), np.bincount(pairs[:, 0], minlength=n))
+    with pytest.raises(ValueError):
+        orc.Graph(4, np.array([0, 5]), np.array([1, 1]))
+
+
+# --------------------------------------------------------------------------------------
+# linearity over sources, multiset semantics, thread-count independence
+# --------------------------------------------------------------------------------------
+def test_linearity_and_multiset(orc):
+    n, u, v = gg.rmat(9, 8, 5)
+    g = orc.Graph(n, u, v)
+    s1 = gg.uniform_sources(n, 100, 1)
+    s2 = gg.uniform_sources(n, 77, 2)
+    a, _, _ = orc.bc(g, s1)
+    b, _, _ = orc.bc(g, s2)
+    c, _, _ = orc.bc(g, np.concatenate([s1, s2]))
+    rel_close(c, a + b, 1e-12)
+    d, _, _ = orc.bc(g, np.concatenate([s1, s1]))
+    rel_close(d, 2 * a, 1e-12)
+    e1, _, _ = orc.bc(g, threads=1)
+    e2, _, _ = orc.bc(g, np.arange(n, dtype=np.uint32), threads=3)
+    rel_close(e1, e2, 1e-12)
