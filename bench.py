@@ -1,0 +1,249 @@
+#!/usr/bin/env python
+"""Benchmark of the Brandes betweenness-centrality hot path on one MI355X.
+
+Default workload: directed R-MAT graph, scale 16 (n = 65,536), edge factor 16, quadrant
+split (0.57, 0.19, 0.19, 0.05), self-loops and repeated pairs removed, seed 16; exact BC
+from all 65,536 sources, FP64 output, uint64 path counts.  One step = one exact BC pass
+(every source: forward sweep, backward sweep, accumulation) with the graph already
+resident in HBM.
+
+Prints one JSON line: nominal GTEPS (sources x edges / s) as `value`, the roofline of the
+search kernel (algorithmic bytes from exact per-call work counters over the kernel's
+HIP-event time), and the CPU oracle timed on a bounded sample of the same sources.
+
+Other workloads (--workload): rmat20 (scale 20, edge factor 16, 1,024 seeded sources),
+lattice (1024 x 1024 lattice with random edge orientation, 1,024 seeded sources), batch
+(4,096 R-MAT graphs of scale 6..12, edge factor 8, exact BC of each in one launch).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic bytes moved by the device design, per reached vertex / examined edge / DAG
+# edge of one source (forward + backward + reset); the derivation is in the design notes.
+BYTES_PER_REACHED = 96
+BYTES_PER_EXAMINED = 16
+BYTES_PER_DAG_EDGE = 24
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(reached, examined, dag):
+    return BYTES_PER_REACHED * reached + BYTES_PER_EXAMINED * examined + BYTES_PER_DAG_EDGE * dag
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ["bc_kernels.hip", "bc_internal.h"]:
+        with open(os.path.join(ROOT, "paper_1409_7764_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, per_launch_scale):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they were taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(workload)
+    except Exception:
+        return None
+    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def cpu_baseline(n, u, v, sources, m, budget_s):
+    """The CPU oracle, untuned, on a bounded prefix of the benchmark's sources."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    threads = max(1, min(threads, oracle.max_threads() if oracle.max_threads() > 0 else threads))
+    g = oracle.Graph(n, u, v)
+    k = min(len(sources), max(threads, 16))
+    t0 = time.perf_counter()
+    oracle.bc(g, sources[:k], threads=threads)
+    dt = time.perf_counter() - t0
+    # grow the sample to roughly the time budget
+    k2 = int(min(len(sources), max(k, k * budget_s / max(dt, 1e-3))))
+    if k2 > k:
+        t0 = time.perf_counter()
+        oracle.bc(g, sources[:k2], threads=threads)
+        dt = time.perf_counter() - t0
+        k = k2
+    return {"value": k * m / dt / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
+            "sample": f"{k} of the {len(sources)} sources (first {k} in benchmark order), "
+                      f"{dt:.1f} s on {threads} threads of {cpu_info()}"}
+
+
+def bench_single(args, torch, bcmi, gg):
+    if args.workload == "rmat16":
+        n, u, v = gg.rmat(16, 16, 16)
+        sources = np.arange(n, dtype=np.uint32)
+        exact = True
+        cfg = {"workload": "rmat16-exact", "graph": "R-MAT scale 16, edge factor 16, a=0.57 b=0.19 c=0.19 "
+               "d=0.05, seed 16, self-loops and duplicates removed", "sources": "all"}
+    elif args.workload == "rmat20":
+        n, u, v = gg.rmat(20, 16, 20)
+        sources = gg.uniform_sources(n, 1024, 2020)
+        exact = False
+        cfg = {"workload": "rmat20-sampled1024", "graph": "R-MAT scale 20, edge factor 16, seed 20",
+               "sources": "1024 uniform without replacement, seed 2020"}
+    else:
+        n, u, v = gg.grid_random_orientation(1024, 1024, 1)
+        sources = gg.uniform_sources(n, 1024, 1024)
+        exact = False
+        cfg = {"workload": "lattice1024-sampled1024", "graph": "1024x1024 lattice, random edge orientation, "
+               "seed 1", "sources": "1024 uniform without replacement, seed 1024"}
+    t0 = time.perf_counter()
+    g = bcmi.bc_build_csr(n, u, v)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    cfg.update({"n": n, "m": g.m})
+    tune = None
+    if args.tune:
+        tune = bcmi.bc_tune(g)
+    tun = bcmi.tuning(**{k: v for k, v in (tune or {}).items()}) if tune else None
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    d_src = torch.from_numpy(sources.view(np.int32)).cuda()
+
+    def step():
+        if exact:
+            return bcmi.bc_exact(g, out=out, tuning=tun, info=True)[1]
+        return bcmi.bc_sampled(g, d_src, out=out, tuning=tun, info=True)[1]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    k = len(sources)
+    kernel_ms = float(np.mean([i["kernel_ms"] for i in infos]))
+    inf = infos[-1]
+    nbytes = algorithmic_bytes(inf["reached"], inf["examined"], inf["dag_edges"])
+    achieved = nbytes / (kernel_ms / 1e3) / 1e9
+    traffic = load_traffic(cfg["workload"], 1)
+    res = {
+        "metric": "GTEPS (sources x edges / s), nominal, exact/sampled BC",
+        "value": k * g.m / (ms_per_step / 1e3) / 1e9,
+        "unit": "GTEPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64 path counts, f64 dependencies and BC",
+        "data": "synthetic",
+        "config": cfg,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_bc_lds" if inf["path"] else "k_bc_global",
+                     "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": nbytes},
+        "extra": {
+            "traversed_gteps": inf["examined"] / (ms_per_step / 1e3) / 1e9,
+            "build_csr_ms": build_ms,
+            "sources": k, "reached": inf["reached"], "examined": inf["examined"],
+            "dag_edges": inf["dag_edges"], "levels_max": inf["levels_max"],
+            "sigma_fp64_fallback_sources": inf["n_sigma_fp64_fallback"],
+            "path": "lds" if inf["path"] else "global", "tuning": tune,
+            "kernel_ms_all": [i["kernel_ms"] for i in infos],
+        },
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(n, u, v, sources, g.m, args.cpu_seconds)
+    g.free()
+    return res
+
+
+def bench_batch(args, torch, bcmi, gg):
+    rng = np.random.default_rng(4096)
+    scales = rng.integers(6, 13, size=4096)
+    specs = [(int(s), 8, 4096_000 + i) for i, s in enumerate(scales)]
+    graphs, coo = [], []
+    t0 = time.perf_counter()
+    for sc, ef, seed in specs:
+        n, u, v = gg.rmat(sc, ef, seed)
+        coo.append((n, u, v))
+        graphs.append(bcmi.bc_build_csr(n, u, v))
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in graphs]
+    tun = None
+    for _ in range(args.warmup):
+        bcmi.bc_batch(graphs, outs, tuning=tun, info=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos.append(bcmi.bc_batch(graphs, outs, tuning=tun, info=True)[1])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    nominal = sum(g.n * g.m for g in graphs)
+    res = {"metric": "GTEPS (sources x edges / s), nominal, batched exact BC", "value": nominal / (ms / 1e3) / 1e9,
+           "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u64 path counts, f64 dependencies and BC", "data": "synthetic",
+           "config": {"workload": "batch4096-rmat6to12-ef8", "graphs": 4096,
+                      "sum_n": int(sum(g.n for g in graphs)), "sum_m": int(sum(g.m for g in graphs))},
+           "extra": {"build_csr_ms_total": build_ms, "kernel_ms": infos[-1][0]["kernel_ms"]}}
+    for g in graphs:
+        g.free()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat20", "lattice", "batch"])
+    ap.add_argument("--tune", action="store_true", help="autotune launch knobs first (untimed)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the method shards over sources with one final sum of the "
+              "per-GPU BC arrays, and this build runs and reports the single-GPU share only "
+              "(--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1409_7764_amd import bcmi, graphgen as gg
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    bcmi.lib()
+    if args.workload == "batch":
+        res = bench_batch(args, torch, bcmi, gg)
+    else:
+        res = bench_single(args, torch, bcmi, gg)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * bcmi -- Brandes betweenness centrality for unweighted directed graphs on AMD Instinct
+ * MI355X (gfx950).  C ABI of libbcmi.so.
+ *
+ * What is computed (section I of S. Quader, "Study of Betweenness Centrality Algorithms
+ * in GPU"): the betweenness of v is the share of pairwise shortest paths passing through
+ * v, here the raw sum over ordered pairs s != v != t of sigma_st(v) / sigma_st, where
+ * sigma_st counts shortest directed s->t paths and sigma_st(v) those with v as an
+ * interior vertex.  Unreachable pairs contribute 0; no normalisation is applied.  The
+ * method is Brandes' (section I): per source, a level-synchronous breadth-first sweep
+ * records BFS distances and shortest-path counts sigma, then a backward sweep over the
+ * levels accumulates the dependencies delta into BC.
+ *
+ * Precision: distances int32 (-1 = unreachable); sigma exact uint64; a source whose
+ * counts exceed 2^64-1 is detected exactly and recounted in double precision; delta and
+ * BC are double precision.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers (hipMalloc'd or torch CUDA tensors) on the
+ *     current HIP device; h_* are host pointers.  The caller owns every array it passes.
+ *     The library owns the graph's CSR/CSC arrays and all scratch memory until the handle
+ *     is freed.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  bc_build_csr, bc_exact,
+ *     bc_sampled and bc_batch are stream-ordered.  Passing a non-NULL `info` makes the call
+ *     wait for its own work on that stream and fills `info` before returning.
+ *   - Calls that share a graph handle must be ordered with respect to each other (one
+ *     stream, or synchronised): the handle's per-source scratch is reused between calls.
+ *   - Return value: BC_OK (0) or a negative error code; bc_last_error() gives a message.
+ *     Output parameters are written only on BC_OK.  No C++ exception crosses this ABI.
+ *   - Vertex ids are uint32 in [0, n); 1 <= n <= 2^31-1; after de-duplication the edge
+ *     count must stay below 2^32.  m = 0 is legal (all BC values are 0).
+ */
+#ifndef BCMI_BC_H
+#define BCMI_BC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define BC_API __attribute__((visibility("default")))
+#else
+#define BC_API
+#endif
+
+typedef int32_t bc_status;
+#define BC_OK 0
+#define BC_PENDING 1     /* bc_serve_poll: request not finished yet */
+#define BC_E_INVAL (-1)  /* null / negative / inconsistent argument */
+#define BC_E_RANGE (-2)  /* vertex id >= n, n out of range, edge count >= 2^32 */
+#define BC_E_NOMEM (-3)  /* device allocation failed, or request larger than a server budget */
+#define BC_E_HIP (-4)    /* HIP runtime error (message via bc_last_error) */
+#define BC_E_STATE (-5)  /* unknown ticket, destroyed handle, stopped server */
+
+typedef struct bc_graph_s* bc_graph;
+typedef struct bc_server_s* bc_server;
+
+/* Launch / strategy knobs.  0 in any field means "choose automatically" (autotuner cache,
+ * or built-in defaults when tuning is switched off with BCMI_TUNE=off). */
+typedef struct {
+    int32_t wg_size;            /* threads per workgroup, multiple of 64 in [64, 1024] */
+    int32_t wgs_per_source;     /* workgroups cooperating on one source (1, 2, 4, 8) */
+    int32_t sources_per_launch; /* concurrent sources (per-source state slots) */
+    int32_t hub_threshold;      /* out-degree from which a vertex is expanded by a whole
+                                   wavefront rather than one thread; < 0 = never */
+    int32_t lds_max_n;          /* largest n run by the LDS-resident path; < 0 = never */
+    int32_t use_graph;          /* 1 = replay a captured hipGraph, -1 = plain launches */
+} bc_tuning;
+
+typedef struct {
+    uint32_t n_sources;             /* sources processed */
+    uint32_t n_sigma_fp64_fallback; /* sources whose path counts overflowed uint64 */
+    uint32_t levels_max;            /* deepest BFS (number of levels) over the sources */
+    uint32_t path;                  /* 0 = global-memory slots, 1 = LDS-resident */
+    double kernel_ms;               /* device time of the call (HIP events) */
+    double t_submit_ms, t_start_ms, t_done_ms; /* bc_serve_poll only: server clock */
+    uint64_t reached;               /* sum over sources of vertices reached (source included) */
+    uint64_t examined;              /* sum over sources of out-edges of reached vertices */
+    uint64_t dag_edges;             /* sum over sources of shortest-path DAG edges */
+} bc_info;
+
+/* Build a graph handle from a pair list (section II-D: edge list A[i]=u, B[i]=v).
+ * d_src, d_dst: m_in uint32 device arrays.  Self-loops and repeated pairs are dropped.
+ * The handle holds CSR (row offsets n+1, successor ids sorted per row) and CSC (the
+ * transpose) on the device.  Errors: BC_E_INVAL (null/negative), BC_E_RANGE (id >= n, or
+ * more than 2^32-1 pairs), BC_E_NOMEM.  The call waits for the build to finish. */
+BC_API bc_status bc_build_csr(int32_t n, int64_t m_in, const uint32_t* d_src, const uint32_t* d_dst,
+                       void* stream, bc_graph* out);
+
+/* n and the de-duplicated edge count. */
+BC_API bc_status bc_graph_info(bc_graph g, int32_t* n, int64_t* m);
+
+/* Device pointers of the handle's CSR (row_ptr n+1, col m) and CSC (col_ptr n+1, row m);
+ * read-only, valid until bc_graph_free. Any output pointer may be NULL. */
+BC_API bc_status bc_graph_arrays(bc_graph g, const uint32_t** d_row_ptr, const uint32_t** d_col,
+                          const uint32_t** d_csc_ptr, const uint32_t** d_csc_row);
+
+/* Release the handle and every device buffer it owns (waits for the device). */
+BC_API bc_status bc_graph_free(bc_graph g);
+
+/* Exact BC (section I): every vertex is a source.  d_bc: n doubles, overwritten. */
+BC_API bc_status bc_exact(bc_graph g, double* d_bc, const bc_tuning* t, void* stream, bc_info* info);
+
+/* Partial BC over a multiset of k sources: d_bc[v] = sum_i [s_i != v] delta_{s_i}(v), no
+ * n/k scaling (the sampled-source approximation cited in section I sums the same terms).
+ * d_sources: k uint32 device array, each < n (checked on the device; a bad id makes the
+ * call return BC_E_RANGE when `info` is given, and is skipped otherwise).  k = 0 zeroes
+ * d_bc. */
+BC_API bc_status bc_sampled(bc_graph g, const uint32_t* d_sources, int32_t k, double* d_bc,
+                     const bc_tuning* t, void* stream, bc_info* info);
+
+/* One source, for inspection: distances and path counts exactly as the forward sweep
+ * leaves them, and the dependencies of the backward sweep.  d_dist (int32 n),
+ * d_sigma_u64 (uint64 n; exact counts, all 0 when overflowed), d_sigma_f64 (double n;
+ * counts as doubles, the double-precision recount when overflowed), d_delta (double n;
+ * delta_s(v), delta_s(s) = reached-1).  Any of the four may be NULL.  *h_overflowed is set
+ * to 1 when the counts exceeded uint64.  Synchronous. */
+BC_API bc_status bc_sssp(bc_graph g, uint32_t s, int32_t* d_dist, uint64_t* d_sigma_u64,
+                  double* d_sigma_f64, double* d_delta, int32_t* h_overflowed, void* stream);
+
+/* Exact BC of many independent graphs in one persistent launch.  d_bcs[i] (n_i doubles,
+ * overwritten) receives graph i's result.  infos (nullable) has num_graphs entries. */
+BC_API bc_status bc_batch(const bc_graph* gs, int32_t num_graphs, double* const* d_bcs,
+                   const bc_tuning* t, void* stream, bc_info* infos);
+
+/* Autotune the launch knobs for this graph (times candidate configurations on a sample of
+ * sources; cached per device and graph class).  Synchronous. */
+BC_API bc_status bc_tune(bc_graph g, bc_tuning* out);
+
+/* ---- serving ------------------------------------------------------------------------
+ * A server owns a device stream and a host thread.  Requests are admitted while the sum
+ * of their device footprints (graph CSR+CSC, per-source state slots, output) fits
+ * `hbm_budget_bytes`; the rest wait in arrival order.  Admitted requests are cut into
+ * source chunks and executed together (continuous batching): requests that arrive while
+ * others run join the next launch.  All bc_serve_* calls are thread-safe. */
+BC_API bc_status bc_serve_create(size_t hbm_budget_bytes, int32_t max_slots, bc_server* out);
+
+/* Submit BC of graph g over h_sources (host array of k ids; NULL = every vertex, exact)
+ * into d_bc (n doubles, overwritten when the request completes).  The graph handle and
+ * d_bc must stay valid until the ticket completes.  Never blocks on device work.
+ * BC_E_NOMEM if the request alone exceeds the server budget. */
+BC_API bc_status bc_serve_submit(bc_server s, bc_graph g, const uint32_t* h_sources, int32_t k,
+                          double* d_bc, uint64_t* ticket);
+
+/* BC_OK and *info filled when the ticket is complete, BC_PENDING otherwise. */
+BC_API bc_status bc_serve_poll(bc_server s, uint64_t ticket, bc_info* info);
+
+/* Stop the server: queued requests are cancelled, running ones are finished first. */
+BC_API bc_status bc_serve_destroy(bc_server s);
+
+/* Thread-local message of the last error on this thread ("" if none). */
+BC_API const char* bc_last_error(void);
+
+/* Library version string. */
+BC_API const char* bc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BCMI_BC_H */

@@ -1,0 +1,132 @@
+// Internal declarations shared by the HIP translation units of libbcmi.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bc.h"
+
+namespace bcmi {
+
+// ---------------------------------------------------------------------------------------
+// error plumbing: every ABI entry point converts failures into a status + message
+// ---------------------------------------------------------------------------------------
+void set_error(const std::string& msg);
+void clear_error();
+
+struct Error {
+    bc_status code;
+    std::string msg;
+};
+
+#define BC_HIP_TRY(expr)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            throw ::bcmi::Error{e_ == hipErrorOutOfMemory ? BC_E_NOMEM : BC_E_HIP,              \
+                                std::string(#expr) + ": " + hipGetErrorString(e_)};             \
+    } while (0)
+
+#define BC_REQUIRE(cond, code, msg)                                                             \
+    do {                                                                                        \
+        if (!(cond)) throw ::bcmi::Error{(code), (msg)};                                        \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------
+// device-side per-vertex record of one source's search.
+//   dist : BFS level, -1 = not reached
+//   val  : forward sweep  -> shortest-path count (uint64 bits, or double bits after overflow)
+//          backward sweep -> psi = (1 + delta) / sigma (double bits), once the vertex's
+//                            level has been finished
+// Keeping dist and the count in one 16-byte record means the count update of a DAG edge
+// touches the cache line the distance test has just fetched.
+// ---------------------------------------------------------------------------------------
+struct alignas(16) VRec {
+    int32_t dist;
+    uint32_t pad;
+    uint64_t val;
+};
+
+// Per-call device counters (written by the kernels, read back for bc_info).
+struct CallStats {
+    uint32_t work_head;      // next work item to claim
+    uint32_t n_done;         // sources completed
+    uint32_t n_overflow;     // sources recounted in double precision
+    uint32_t levels_max;     // deepest search
+    uint32_t bad_source;     // sources with id >= n (skipped)
+    uint32_t pad[3];
+    uint64_t reached;        // sum over sources of reached vertices (source included)
+    uint64_t examined;       // sum over sources of out-edges of reached vertices
+    uint64_t dag_edges;      // sum over sources of shortest-path DAG edges
+    uint64_t pad2;
+};
+
+// Launch knobs after defaults / tuning are applied.
+struct Knobs {
+    int wg_size = 256;
+    int team = 1;                // workgroups per source
+    int teams = 0;               // concurrent sources; 0 = fill the device
+    int hub = 32;                // wavefront-per-vertex threshold
+    int lds_max_n = 4096;
+    bool use_graph = true;
+};
+
+// Graph handle (the opaque bc_graph).
+struct Graph {
+    int device = 0;
+    int32_t n = 0;
+    uint32_t m = 0;
+    uint32_t* row_ptr = nullptr;   // n+1
+    uint32_t* col = nullptr;       // m
+    uint32_t* csc_ptr = nullptr;   // n+1
+    uint32_t* csc_row = nullptr;   // m
+    uint32_t max_out_degree = 0;
+    // per-source scratch, grown on demand and reused between calls
+    void* slots = nullptr;
+    CallStats* stats = nullptr;    // device
+    std::mutex mu;
+    ~Graph();
+};
+
+// Device properties used for launch sizing.
+struct DevInfo {
+    int cus = 256;
+    int lds_per_block = 65536;
+    int lds_per_cu = 163840;
+    int max_threads = 1024;
+    std::string name;
+};
+const DevInfo& dev_info(int device);
+
+// ---- CSR builder (csr_build.hip) --------------------------------------------------------
+void build_csr_device(int32_t n, int64_t m_in, const uint32_t* d_src, const uint32_t* d_dst,
+                      hipStream_t stream, Graph& g);
+
+// ---- per-source kernels (bc_kernels.hip) -------------------------------------------------
+struct RunArgs {
+    const Graph* g;
+    const uint32_t* sources;   // nullable: item i is source i
+    uint32_t num_items;
+    double* bc;                // nullable (bc_sssp)
+    // optional export of one source's arrays (bc_sssp)
+    int32_t* ex_dist = nullptr;
+    uint64_t* ex_sigma = nullptr;
+    double* ex_sigma_f = nullptr;
+    double* ex_delta = nullptr;
+};
+// Enqueue a full BC pass over the given sources on `stream` (zeroes bc first).  Returns
+// which path ran (0 global slots, 1 LDS).
+int run_sources(const RunArgs& a, const Knobs& k, hipStream_t stream, Graph& g);
+void read_stats(Graph& g, hipStream_t stream, CallStats* out);
+
+// ---- tuning (tune.hip) -------------------------------------------------------------------
+Knobs resolve_knobs(Graph& g, const bc_tuning* t);
+Knobs default_knobs(const Graph& g);
+bool tuning_enabled();
+
+}  // namespace bcmi

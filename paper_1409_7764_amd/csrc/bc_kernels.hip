@@ -1,0 +1,1079 @@
+// Brandes betweenness centrality, per-source kernels for gfx950.
+//
+// For one source s (section I, Brandes' method):
+//   forward : level-synchronous breadth-first sweep from s.  For frontier vertex v at level d
+//             and successor w: the first visitor claims w for level d+1 (compare-and-swap on
+//             its distance) and appends it to the next frontier; every edge with
+//             dist[w] = d+1 adds sigma[v] into sigma[w] (64-bit integer atomics; a carry out
+//             of bit 63 flags the source, which is then recounted in double precision).
+//   backward: levels from the deepest to 0.  Each vertex v of level d owns its own update,
+//             pulling from its successors w (dist[w] = d+1):
+//                 delta[v] = sigma[v] * sum_w psi[w],   psi[w] = (1 + delta[w]) / sigma[w]
+//             which is the successor form of Brandes' dependency recurrence.  No atomics on
+//             delta, no predecessor lists (the paper's n^2 predecessor array is replaced by
+//             the distance test).  BC[v] += delta[v] for v != s (FP64 atomics).
+//
+// Scheduling inside a workgroup (one workgroup per source).  A frontier is processed in
+// chunks of WG vertices held in LDS.  Per chunk the vertices are classified by out-degree:
+//   * hubs (degree >= hub threshold) are cut into pieces of kPiece edges, and each piece is
+//     expanded by a whole wavefront: 64 consecutive col[] entries per step, coalesced;
+//   * the remaining vertices are expanded either thread-per-vertex (when the chunk's
+//     largest degree is small, e.g. lattice-like levels) or thread-per-edge over the
+//     chunk's flattened edge list (degree prefix sum in LDS, owner found by binary search),
+//     which balances skewed degree mixes.
+//
+// Two homes for the per-source state:
+//   * global memory: one slot per concurrently running source (16-byte {dist, count/psi}
+//     record per vertex, BFS queue, level offsets); any graph size;
+//   * LDS: the whole state of one source in the workgroup's LDS (12 bytes per vertex:
+//     16-bit distance, 64-bit count/psi, 16-bit queue entry) for small graphs.
+// Both run the same level code through a small state policy.
+#include "bc_internal.h"
+
+#include <algorithm>
+
+namespace bcmi {
+
+// ---- launch-level structures (shared with the host side below) ---------------------------
+struct WorkDesc {
+    const uint32_t* row_ptr;
+    const uint32_t* col;
+    double* bc;
+    const uint32_t* sources;   // nullable: local item i is source i
+    uint32_t* counters;        // nullable: per-descriptor {done, overflowed, levels_max, bad}
+    int32_t n;
+    uint32_t item_begin;
+    uint32_t num_items;
+    uint32_t pad;
+};
+
+struct LaunchArgs {
+    const WorkDesc* descs;
+    uint32_t ndesc;
+    uint32_t total_items;
+    CallStats* stats;
+    uint32_t hub;
+    uint32_t tpv_max;          // chunk max degree up to which thread-per-vertex is used
+    // global-memory slots
+    VRec* rec;
+    uint32_t* queue;
+    uint32_t* lvl;
+    uint32_t slot_n;
+    uint32_t lds_n;            // LDS path: vertex capacity
+    uint32_t zero_outputs;     // zero each descriptor's BC output and counters first
+    // export of one source (inspection entry point)
+    int32_t* ex_dist;
+    uint64_t* ex_sigma;
+    double* ex_sigma_f;
+    double* ex_delta;
+};
+
+namespace {
+
+constexpr uint32_t kPiece = 256;     // hub edges per wavefront work piece
+constexpr uint16_t kUnseen16 = 0xffff;
+
+__device__ __forceinline__ unsigned lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+__device__ __forceinline__ double u2d(uint64_t x) { return __longlong_as_double((long long)x); }
+__device__ __forceinline__ uint64_t d2u(double x) { return (uint64_t)__double_as_longlong(x); }
+
+template <class T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x = max(x, (T)__shfl_xor(x, d, 64));
+    return x;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const unsigned lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (unsigned)d) x += y;
+    }
+    return x;
+}
+
+template <int WG>
+struct Scratch {
+    uint32_t wsum[3][WG / 64];
+    uint32_t scan[WG + 1];     // edge offsets of non-hub vertices in the chunk
+    uint32_t pscan[WG + 1];    // piece offsets of hub vertices in the chunk
+    uint32_t beg[WG];
+    uint32_t deg[WG];
+    uint64_t sig[WG];
+    double acc[WG];
+    uint32_t tail;             // next free queue position
+    uint32_t ovf;              // a 64-bit count carried
+    uint32_t item, desc;
+};
+
+// largest j in [0, WG) with a[j] <= p (a non-decreasing, a[0] = 0 <= p)
+template <int WG>
+__device__ __forceinline__ uint32_t find_owner(const uint32_t* a, uint32_t p) {
+    uint32_t lo = 0, len = WG;
+    while (len > 1) {
+        const uint32_t half = len >> 1;
+        if (a[lo + half] <= p) lo += half;
+        len -= half;
+    }
+    return lo;
+}
+
+// Chunk classification: offsets of non-hub edges, offsets of hub pieces, largest non-hub
+// degree.  Two block barriers.
+template <int WG>
+__device__ __forceinline__ void classify_chunk(Scratch<WG>& L, uint32_t deg, bool is_hub, uint32_t& small_off,
+                                               uint32_t& small_total, uint32_t& piece_off, uint32_t& piece_total,
+                                               uint32_t& max_small) {
+    const unsigned lane = lane_id(), w = threadIdx.x / 64;
+    const uint32_t a = is_hub ? 0u : deg;
+    const uint32_t b = is_hub ? (deg + kPiece - 1) / kPiece : 0u;
+    const uint32_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
+    const uint32_t mx = wave_max(a);
+    if (lane == 63) {
+        L.wsum[0][w] = ia;
+        L.wsum[1][w] = ib;
+        L.wsum[2][w] = mx;
+    }
+    __syncthreads();
+    uint32_t ba = 0, bb = 0, ta = 0, tb = 0, tm = 0;
+#pragma unroll
+    for (int i = 0; i < WG / 64; ++i) {
+        const uint32_t x = L.wsum[0][i], y = L.wsum[1][i];
+        if (i < (int)w) { ba += x; bb += y; }
+        ta += x;
+        tb += y;
+        tm = max(tm, L.wsum[2][i]);
+    }
+    small_off = ba + ia - a;
+    piece_off = bb + ib - b;
+    small_total = ta;
+    piece_total = tb;
+    max_small = tm;
+}
+
+// ---- per-source state policies ------------------------------------------------------------
+struct GState {
+    VRec* rec;
+    uint32_t* queue;
+    uint32_t* lvl;
+
+    __device__ __forceinline__ int claim(uint32_t w, int d1, bool& fresh) {
+        fresh = false;
+        int dw = rec[w].dist;
+        if (dw < 0) {
+            const int old = atomicCAS(&rec[w].dist, -1, d1);
+            if (old < 0) {
+                fresh = true;
+                dw = d1;
+            } else {
+                dw = old;
+            }
+        }
+        return dw;
+    }
+    __device__ __forceinline__ int dist(uint32_t v) const { return rec[v].dist; }
+    __device__ __forceinline__ uint64_t val(uint32_t v) const { return rec[v].val; }
+    __device__ __forceinline__ void set_val(uint32_t v, uint64_t x) { rec[v].val = x; }
+    __device__ __forceinline__ bool add_u64(uint32_t w, uint64_t s) {
+        const unsigned long long old = atomicAdd((unsigned long long*)&rec[w].val, (unsigned long long)s);
+        return old + s < old;
+    }
+    __device__ __forceinline__ void add_f64(uint32_t w, uint64_t s) { unsafeAtomicAdd((double*)&rec[w].val, u2d(s)); }
+    __device__ __forceinline__ double psi_if_level(uint32_t w, int d1) const {
+        const VRec r = rec[w];
+        return r.dist == d1 ? u2d(r.val) : 0.0;
+    }
+    __device__ __forceinline__ uint32_t q(uint32_t i) const { return queue[i]; }
+    __device__ __forceinline__ void q_set(uint32_t i, uint32_t w) { queue[i] = w; }
+    __device__ __forceinline__ void seed(uint32_t s, uint64_t one) {
+        rec[s].dist = 0;
+        rec[s].val = one;
+        queue[0] = s;
+        lvl[0] = 0;
+        lvl[1] = 1;
+    }
+    __device__ __forceinline__ void set_level_end(int d, uint32_t end) { lvl[d + 1] = end; }
+    __device__ __forceinline__ uint32_t level_begin(int d, uint32_t) const { return lvl[d]; }
+    __device__ __forceinline__ void reset(uint32_t v) {
+        VRec r;
+        r.dist = -1;
+        r.pad = 0;
+        r.val = 0;
+        rec[v] = r;
+    }
+    // level boundary: make this workgroup's global writes visible and drop stale L1 lines
+    __device__ __forceinline__ void barrier() const {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+};
+
+struct LState {
+    uint16_t* dist16;   // 0xffff = not reached
+    uint64_t* vals;
+    uint16_t* queue;
+
+    __device__ __forceinline__ int claim(uint32_t w, int d1, bool& fresh) {
+        fresh = false;
+        const uint16_t cur = dist16[w];
+        if (cur != kUnseen16) return cur;
+        uint32_t* word = reinterpret_cast<uint32_t*>(dist16) + (w >> 1);
+        const int sh = (w & 1) * 16;
+        uint32_t old = *word;
+        for (;;) {
+            const uint32_t h = (old >> sh) & 0xffffu;
+            if (h != kUnseen16) return (int)h;
+            const uint32_t nw = (old & ~(0xffffu << sh)) | ((uint32_t)d1 << sh);
+            const uint32_t prev = atomicCAS(word, old, nw);
+            if (prev == old) {
+                fresh = true;
+                return d1;
+            }
+            old = prev;
+        }
+    }
+    __device__ __forceinline__ int dist(uint32_t v) const {
+        const uint16_t d = dist16[v];
+        return d == kUnseen16 ? -1 : (int)d;
+    }
+    __device__ __forceinline__ uint64_t val(uint32_t v) const { return vals[v]; }
+    __device__ __forceinline__ void set_val(uint32_t v, uint64_t x) { vals[v] = x; }
+    __device__ __forceinline__ bool add_u64(uint32_t w, uint64_t s) {
+        const unsigned long long old = atomicAdd((unsigned long long*)&vals[w], (unsigned long long)s);
+        return old + s < old;
+    }
+    __device__ __forceinline__ void add_f64(uint32_t w, uint64_t s) { atomicAdd((double*)&vals[w], u2d(s)); }
+    __device__ __forceinline__ double psi_if_level(uint32_t w, int d1) const {
+        return dist16[w] == (uint16_t)d1 ? u2d(vals[w]) : 0.0;
+    }
+    __device__ __forceinline__ uint32_t q(uint32_t i) const { return queue[i]; }
+    __device__ __forceinline__ void q_set(uint32_t i, uint32_t w) { queue[i] = (uint16_t)w; }
+    __device__ __forceinline__ void seed(uint32_t s, uint64_t one) {
+        dist16[s] = 0;
+        vals[s] = one;
+        queue[0] = (uint16_t)s;
+    }
+    __device__ __forceinline__ void set_level_end(int, uint32_t) {}
+    // the queue is in BFS order, so the levels are contiguous: first entry with dist >= d
+    __device__ __forceinline__ uint32_t level_begin(int d, uint32_t hi) const {
+        uint32_t lo = 0;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((int)dist16[queue[mid]] < d) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    }
+    __device__ __forceinline__ void reset(uint32_t v) {
+        dist16[v] = kUnseen16;
+        vals[v] = 0;
+    }
+    __device__ __forceinline__ void barrier() const { __syncthreads(); }
+};
+
+// ---- forward sweep ----------------------------------------------------------------------------
+template <bool F64, int WG, class S>
+__device__ __forceinline__ void forward_edge(S& st, Scratch<WG>& L, bool ok, uint32_t w, uint64_t s, int d1,
+                                             uint32_t& dag) {
+    bool fresh = false;
+    if (ok) {
+        const int dw = st.claim(w, d1, fresh);
+        if (dw == d1) {
+            ++dag;
+            if (F64) st.add_f64(w, s);
+            else if (st.add_u64(w, s)) L.ovf = 1u;
+        }
+    }
+    const uint64_t mask = __ballot(fresh);
+    if (mask) {
+        const unsigned lane = lane_id();
+        const unsigned leader = __builtin_ctzll(mask);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&L.tail, (uint32_t)__builtin_popcountll(mask));
+        base = __shfl(base, leader, 64);
+        if (fresh) st.q_set(base + (uint32_t)__builtin_popcountll(mask & lanemask_lt()), w);
+    }
+}
+
+template <bool F64, int WG, class S>
+__device__ void expand_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__ row_ptr,
+                             const uint32_t* __restrict__ col, uint32_t lo, uint32_t hi, int d, uint32_t hub,
+                             uint32_t tpv_max, uint32_t& exam, uint32_t& dag) {
+    const unsigned tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
+    constexpr unsigned NW = WG / 64;
+    const int d1 = d + 1;
+    for (uint32_t c0 = lo; c0 < hi; c0 += WG) {
+        const uint32_t i = c0 + tid;
+        const bool valid = i < hi;
+        uint32_t v = 0, beg = 0, deg = 0;
+        uint64_t sv = 0;
+        if (valid) {
+            v = st.q(i);
+            beg = row_ptr[v];
+            deg = row_ptr[v + 1] - beg;
+            sv = st.val(v);
+            exam += deg;
+        }
+        const bool is_hub = valid && deg >= hub;
+        uint32_t so, stot, po, ptot, mx;
+        classify_chunk<WG>(L, deg, is_hub, so, stot, po, ptot, mx);
+        if (ptot == 0 && mx <= tpv_max) {
+            // thread per vertex: every lane walks its own short list
+            const uint32_t my = is_hub ? 0u : deg;
+            const uint32_t wm = wave_max(my);
+            for (uint32_t t = 0; t < wm; ++t) {
+                const bool ok = t < my;
+                const uint32_t w = ok ? col[beg + t] : 0u;
+                forward_edge<F64>(st, L, ok, w, sv, d1, dag);
+            }
+            __syncthreads();
+            continue;
+        }
+        L.scan[tid] = so;
+        L.pscan[tid] = po;
+        L.beg[tid] = beg;
+        L.deg[tid] = deg;
+        L.sig[tid] = sv;
+        __syncthreads();
+        // thread per edge over the non-hub vertices of the chunk
+        for (uint32_t p0 = 0; p0 < stot; p0 += WG) {
+            const uint32_t p = p0 + tid;
+            const bool ok = p < stot;
+            uint32_t w = 0;
+            uint64_t s = 0;
+            if (ok) {
+                const uint32_t j = find_owner<WG>(L.scan, p);
+                w = col[L.beg[j] + (p - L.scan[j])];
+                s = L.sig[j];
+            }
+            forward_edge<F64>(st, L, ok, w, s, d1, dag);
+        }
+        // wavefront per hub piece: lanes read 64 consecutive successors per step
+        for (uint32_t pc = wave; pc < ptot; pc += NW) {
+            const uint32_t j = find_owner<WG>(L.pscan, pc);
+            const uint32_t e0 = (pc - L.pscan[j]) * kPiece;
+            const uint32_t e1 = min(L.deg[j], e0 + kPiece);
+            const uint32_t b = L.beg[j];
+            const uint64_t s = L.sig[j];
+            for (uint32_t e = e0; e < e1; e += 64) {
+                const bool ok = e + lane < e1;
+                const uint32_t w = ok ? col[b + e + lane] : 0u;
+                forward_edge<F64>(st, L, ok, w, s, d1, dag);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---- backward sweep ---------------------------------------------------------------------------
+template <bool F64, int WG, class S>
+__device__ void accumulate_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__ row_ptr,
+                                 const uint32_t* __restrict__ col, uint32_t lo, uint32_t hi, int d, uint32_t hub,
+                                 uint32_t tpv_max, uint32_t src, double* __restrict__ bc, double* ex_delta) {
+    const unsigned tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
+    constexpr unsigned NW = WG / 64;
+    const int d1 = d + 1;
+    for (uint32_t c0 = lo; c0 < hi; c0 += WG) {
+        const uint32_t i = c0 + tid;
+        const bool valid = i < hi;
+        uint32_t v = 0, beg = 0, deg = 0;
+        uint64_t sv = 0;
+        if (valid) {
+            v = st.q(i);
+            beg = row_ptr[v];
+            deg = row_ptr[v + 1] - beg;
+            sv = st.val(v);
+        }
+        const bool is_hub = valid && deg >= hub;
+        uint32_t so, stot, po, ptot, mx;
+        classify_chunk<WG>(L, deg, is_hub, so, stot, po, ptot, mx);
+        double own = 0.0;
+        if (ptot == 0 && mx <= tpv_max) {
+            const uint32_t my = is_hub ? 0u : deg;
+            for (uint32_t t = 0; t < my; ++t) own += st.psi_if_level(col[beg + t], d1);
+        } else {
+            L.scan[tid] = so;
+            L.pscan[tid] = po;
+            L.beg[tid] = beg;
+            L.deg[tid] = deg;
+            L.acc[tid] = 0.0;
+            __syncthreads();
+            for (uint32_t p0 = 0; p0 < stot; p0 += WG) {
+                const uint32_t p = p0 + tid;
+                if (p < stot) {
+                    const uint32_t j = find_owner<WG>(L.scan, p);
+                    const double c = st.psi_if_level(col[L.beg[j] + (p - L.scan[j])], d1);
+                    if (c != 0.0) atomicAdd(&L.acc[j], c);
+                }
+            }
+            for (uint32_t pc = wave; pc < ptot; pc += NW) {
+                const uint32_t j = find_owner<WG>(L.pscan, pc);
+                const uint32_t e0 = (pc - L.pscan[j]) * kPiece;
+                const uint32_t e1 = min(L.deg[j], e0 + kPiece);
+                const uint32_t b = L.beg[j];
+                double part = 0.0;
+                for (uint32_t e = e0 + lane; e < e1; e += 64) part += st.psi_if_level(col[b + e], d1);
+                part = wave_sum(part);
+                if (lane == 0 && part != 0.0) atomicAdd(&L.acc[j], part);
+            }
+            __syncthreads();
+            own = L.acc[tid];
+        }
+        if (valid) {
+            const double sigma = F64 ? u2d(sv) : (double)sv;
+            const double delta = sigma * own;
+            st.set_val(v, d2u((1.0 + delta) / sigma));
+            if (v != src && delta != 0.0) unsafeAtomicAdd(&bc[v], delta);
+            if (ex_delta) ex_delta[v] = delta;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- one source -------------------------------------------------------------------------------
+template <int WG, class S>
+__device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s, const LaunchArgs& a) {
+    const unsigned tid = threadIdx.x;
+    bool f64 = false;
+    uint32_t count = 0;
+    int nlev = 0;
+    uint32_t exam = 0, dag = 0;
+    for (;;) {   // exact 64-bit counts first; a second pass in double precision after a carry
+        exam = 0;
+        dag = 0;
+        if (tid == 0) {
+            st.seed(s, f64 ? d2u(1.0) : 1ull);
+            L.tail = 1;
+            L.ovf = 0;
+        }
+        st.barrier();
+        uint32_t lo = 0, hi = 1;
+        int d = 0;
+        bool overflowed = false;
+        for (;;) {
+            if (f64) expand_level<true, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+            else expand_level<false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+            st.barrier();
+            const uint32_t tail = L.tail;
+            const bool ov = L.ovf != 0u;
+            __syncthreads();
+            if (!f64 && ov) {
+                overflowed = true;
+                count = tail;
+                break;
+            }
+            if (tail == hi) {
+                count = tail;
+                break;
+            }
+            if (tid == 0) st.set_level_end(d + 1, tail);
+            lo = hi;
+            hi = tail;
+            ++d;
+        }
+        nlev = d + 1;
+        if (!overflowed) break;
+        for (uint32_t i = tid; i < count; i += WG) st.reset(st.q(i));
+        st.barrier();
+        f64 = true;
+    }
+    if (a.ex_dist || a.ex_sigma || a.ex_sigma_f) {   // inspection: the forward sweep's result
+        for (uint32_t i = tid; i < count; i += WG) {
+            const uint32_t v = st.q(i);
+            const uint64_t x = st.val(v);
+            if (a.ex_dist) a.ex_dist[v] = st.dist(v);
+            if (a.ex_sigma) a.ex_sigma[v] = f64 ? 0ull : x;
+            if (a.ex_sigma_f) a.ex_sigma_f[v] = f64 ? u2d(x) : (double)x;
+        }
+    }
+    uint32_t hi = count;
+    for (int dd = nlev - 1; dd >= 0; --dd) {
+        const uint32_t lo = st.level_begin(dd, hi);
+        if (f64) accumulate_level<true, WG>(st, L, D.row_ptr, D.col, lo, hi, dd, a.hub, a.tpv_max, s, D.bc, a.ex_delta);
+        else accumulate_level<false, WG>(st, L, D.row_ptr, D.col, lo, hi, dd, a.hub, a.tpv_max, s, D.bc, a.ex_delta);
+        st.barrier();
+        hi = lo;
+    }
+    for (uint32_t i = tid; i < count; i += WG) st.reset(st.q(i));
+    // per-source work counters (examined edges, DAG edges), reduced over the workgroup
+    {
+        const unsigned lane = lane_id(), w = tid / 64;
+        const uint32_t e_w = wave_sum_u32(exam), g_w = wave_sum_u32(dag);
+        if (lane == 0) {
+            L.wsum[0][w] = e_w;
+            L.wsum[1][w] = g_w;
+        }
+    }
+    st.barrier();
+    if (tid == 0) {
+        uint64_t e_all = 0, g_all = 0;
+        for (int i = 0; i < WG / 64; ++i) {
+            e_all += L.wsum[0][i];
+            g_all += L.wsum[1][i];
+        }
+        atomicAdd((unsigned long long*)&a.stats->reached, (unsigned long long)count);
+        atomicAdd((unsigned long long*)&a.stats->examined, (unsigned long long)e_all);
+        atomicAdd((unsigned long long*)&a.stats->dag_edges, (unsigned long long)g_all);
+        atomicAdd(&a.stats->n_done, 1u);
+        if (f64) atomicAdd(&a.stats->n_overflow, 1u);
+        atomicMax(&a.stats->levels_max, (uint32_t)nlev);
+        if (D.counters) {
+            if (f64) atomicAdd(&D.counters[1], 1u);
+            atomicMax(&D.counters[2], (uint32_t)nlev);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomicAdd(&D.counters[0], 1u);
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t find_desc(const WorkDesc* descs, uint32_t ndesc, uint32_t item) {
+    uint32_t lo = 0, len = ndesc;
+    while (len > 1) {
+        const uint32_t half = len >> 1;
+        if (descs[lo + half].item_begin <= item) lo += half;
+        len -= half;
+    }
+    return lo;
+}
+
+// claims the next work item for the whole workgroup; false when the list is exhausted
+template <int WG>
+__device__ __forceinline__ bool claim_item(const LaunchArgs& a, Scratch<WG>& L, uint32_t& di, uint32_t& s,
+                                           uint32_t n_cap) {
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t item = atomicAdd(&a.stats->work_head, 1u);
+            L.item = item;
+            L.desc = item < a.total_items ? find_desc(a.descs, a.ndesc, item) : 0u;
+        }
+        __syncthreads();
+        const uint32_t item = L.item;
+        di = L.desc;
+        __syncthreads();
+        if (item >= a.total_items) return false;
+        const WorkDesc& D = a.descs[di];
+        const uint32_t local = item - D.item_begin;
+        s = D.sources ? D.sources[local] : local;
+        if (s < (uint32_t)D.n && (uint32_t)D.n <= n_cap) return true;
+        if (threadIdx.x == 0) {
+            atomicAdd(&a.stats->bad_source, 1u);
+            if (D.counters) {
+                atomicAdd(&D.counters[3], 1u);
+                atomicAdd(&D.counters[0], 1u);
+            }
+        }
+    }
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_bc_global(LaunchArgs a) {
+    __shared__ Scratch<WG> L;
+    GState st;
+    st.rec = a.rec + (size_t)blockIdx.x * a.slot_n;
+    st.queue = a.queue + (size_t)blockIdx.x * a.slot_n;
+    st.lvl = a.lvl + (size_t)blockIdx.x * ((size_t)a.slot_n + 1);
+    uint32_t di, s;
+    while (claim_item<WG>(a, L, di, s, a.slot_n)) one_source<WG>(st, L, a.descs[di], s, a);
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_bc_lds(LaunchArgs a) {
+    __shared__ Scratch<WG> L;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t cap = a.lds_n;
+    const uint32_t cap2 = (cap + 3) & ~3u;
+    LState st;
+    st.vals = reinterpret_cast<uint64_t*>(smem);
+    st.dist16 = reinterpret_cast<uint16_t*>(smem + 8 * (size_t)cap2);
+    st.queue = st.dist16 + cap2;
+    for (uint32_t i = threadIdx.x; i < cap2; i += WG) {
+        st.vals[i] = 0;
+        st.dist16[i] = kUnseen16;
+    }
+    __syncthreads();
+    uint32_t di, s;
+    while (claim_item<WG>(a, L, di, s, cap)) one_source<WG>(st, L, a.descs[di], s, a);
+}
+
+__global__ void k_prepare(const WorkDesc* descs, uint32_t ndesc, CallStats* stats, uint32_t zero_outputs) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < sizeof(CallStats) / 4)
+        reinterpret_cast<uint32_t*>(stats)[threadIdx.x] = 0u;
+    if (!zero_outputs) return;
+    for (uint32_t d = blockIdx.y; d < ndesc; d += gridDim.y) {
+        if (blockIdx.x == 0 && threadIdx.x < 4 && descs[d].counters) descs[d].counters[threadIdx.x] = 0u;
+        double* bc = descs[d].bc;
+        const uint32_t n = (uint32_t)descs[d].n;
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) bc[i] = 0.0;
+    }
+}
+
+__global__ void k_fill_rec(VRec* rec, size_t count) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        VRec r;
+        r.dist = -1;
+        r.pad = 0;
+        r.val = 0;
+        rec[i] = r;
+    }
+}
+
+__global__ void k_fill_export(int32_t* dist, uint64_t* sigma, double* sigma_f, double* delta, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (dist) dist[i] = -1;
+        if (sigma) sigma[i] = 0;
+        if (sigma_f) sigma_f[i] = 0.0;
+        if (delta) delta[i] = 0.0;
+    }
+}
+
+}  // namespace
+
+// ======================================================================================
+// host side
+// ======================================================================================
+namespace {
+
+template <int WG>
+void launch_global(const LaunchArgs& a, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_bc_global<WG>, dim3(grid), dim3(WG), 0, st, a);
+}
+template <int WG>
+void launch_lds(const LaunchArgs& a, unsigned grid, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(k_bc_lds<WG>, dim3(grid), dim3(WG), lds, st, a);
+}
+
+const void* global_fn(int wg) {
+    switch (wg) {
+        case 64: return (const void*)k_bc_global<64>;
+        case 128: return (const void*)k_bc_global<128>;
+        case 256: return (const void*)k_bc_global<256>;
+        case 512: return (const void*)k_bc_global<512>;
+        default: return (const void*)k_bc_global<1024>;
+    }
+}
+const void* lds_fn(int wg) {
+    switch (wg) {
+        case 64: return (const void*)k_bc_lds<64>;
+        case 128: return (const void*)k_bc_lds<128>;
+        case 256: return (const void*)k_bc_lds<256>;
+        case 512: return (const void*)k_bc_lds<512>;
+        default: return (const void*)k_bc_lds<1024>;
+    }
+}
+
+int norm_wg(int wg) {
+    if (wg <= 64) return 64;
+    if (wg <= 128) return 128;
+    if (wg <= 256) return 256;
+    if (wg <= 512) return 512;
+    return 1024;
+}
+
+}  // namespace
+
+size_t scratch_bytes(int wg) {
+    switch (wg) {
+        case 64: return sizeof(Scratch<64>);
+        case 128: return sizeof(Scratch<128>);
+        case 256: return sizeof(Scratch<256>);
+        case 512: return sizeof(Scratch<512>);
+        default: return sizeof(Scratch<1024>);
+    }
+}
+
+size_t lds_state_bytes(uint32_t cap) {
+    const size_t cap2 = (cap + 3) & ~3u;
+    return cap2 * 8 + cap2 * 2 + cap2 * 2;
+}
+
+int occupancy_blocks(bool lds_path, int wg, size_t dyn_lds) {
+    int per_cu = 0;
+    const void* fn = lds_path ? lds_fn(wg) : global_fn(wg);
+    if (lds_path && dyn_lds > 0)
+        BC_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds));
+    BC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, wg, dyn_lds));
+    return per_cu;
+}
+
+// Device-resident slot pool for the global-memory path.
+struct SlotPool {
+    VRec* rec = nullptr;
+    uint32_t* queue = nullptr;
+    uint32_t* lvl = nullptr;
+    uint32_t slot_n = 0;
+    int slots = 0;
+};
+
+void pool_free(SlotPool& p) {
+    if (p.rec) (void)hipFree(p.rec);
+    if (p.queue) (void)hipFree(p.queue);
+    if (p.lvl) (void)hipFree(p.lvl);
+    p = SlotPool{};
+}
+
+size_t pool_bytes(uint32_t slot_n, int slots) {
+    return (size_t)slots * ((size_t)slot_n * (sizeof(VRec) + 4) + 4 * ((size_t)slot_n + 1));
+}
+
+void pool_ensure(SlotPool& p, uint32_t slot_n, int slots, hipStream_t st) {
+    if (p.rec && p.slot_n >= slot_n && p.slots >= slots) return;
+    BC_HIP_TRY(hipStreamSynchronize(st));
+    pool_free(p);
+    BC_HIP_TRY(hipMalloc((void**)&p.rec, (size_t)slots * slot_n * sizeof(VRec)));
+    BC_HIP_TRY(hipMalloc((void**)&p.queue, (size_t)slots * slot_n * 4));
+    BC_HIP_TRY(hipMalloc((void**)&p.lvl, (size_t)slots * ((size_t)slot_n + 1) * 4));
+    p.slot_n = slot_n;
+    p.slots = slots;
+    const size_t count = (size_t)slots * slot_n;
+    hipLaunchKernelGGL(k_fill_rec, dim3((unsigned)std::min<size_t>((count + 255) / 256, 65536)), dim3(256), 0, st,
+                       p.rec, count);
+    BC_HIP_TRY(hipGetLastError());
+}
+
+// Plans one launch over a list of work descriptors (already on the device) and enqueues it.
+struct LaunchPlan {
+    bool lds_path = false;
+    int wg = 256;
+    unsigned grid = 0;
+    size_t dyn_lds = 0;
+    LaunchArgs args{};
+};
+
+void enqueue_plan(const LaunchPlan& p, hipStream_t st, uint32_t max_n) {
+    // zero outputs and counters, then the persistent search kernel
+    const unsigned gx = std::max(1u, std::min<unsigned>((max_n + 255) / 256, 1024));
+    const unsigned gy = std::max(1u, std::min<unsigned>(p.args.ndesc, 4096));
+    hipLaunchKernelGGL(k_prepare, dim3(gx, gy), dim3(256), 0, st, p.args.descs, p.args.ndesc, p.args.stats,
+                       p.args.zero_outputs);
+    BC_HIP_TRY(hipGetLastError());
+    if (p.args.ex_dist || p.args.ex_sigma || p.args.ex_sigma_f || p.args.ex_delta) {
+        hipLaunchKernelGGL(k_fill_export, dim3(std::max(1u, std::min<unsigned>((max_n + 255) / 256, 1024))), dim3(256),
+                           0, st, p.args.ex_dist, p.args.ex_sigma, p.args.ex_sigma_f, p.args.ex_delta, max_n);
+        BC_HIP_TRY(hipGetLastError());
+    }
+    if (p.args.total_items == 0 || p.grid == 0) return;
+    if (p.lds_path) {
+        switch (p.wg) {
+            case 64: launch_lds<64>(p.args, p.grid, p.dyn_lds, st); break;
+            case 128: launch_lds<128>(p.args, p.grid, p.dyn_lds, st); break;
+            case 256: launch_lds<256>(p.args, p.grid, p.dyn_lds, st); break;
+            case 512: launch_lds<512>(p.args, p.grid, p.dyn_lds, st); break;
+            default: launch_lds<1024>(p.args, p.grid, p.dyn_lds, st); break;
+        }
+    } else {
+        switch (p.wg) {
+            case 64: launch_global<64>(p.args, p.grid, st); break;
+            case 128: launch_global<128>(p.args, p.grid, st); break;
+            case 256: launch_global<256>(p.args, p.grid, st); break;
+            case 512: launch_global<512>(p.args, p.grid, st); break;
+            default: launch_global<1024>(p.args, p.grid, st); break;
+        }
+    }
+    BC_HIP_TRY(hipGetLastError());
+}
+
+// Decide path and launch shape for `items` work items over graphs of at most max_n vertices.
+LaunchPlan make_plan(const Knobs& k, uint32_t max_n, uint32_t items, int device) {
+    LaunchPlan p;
+    const DevInfo& di = dev_info(device);
+    p.wg = norm_wg(k.wg_size);
+    p.lds_path = k.lds_max_n > 0 && max_n <= (uint32_t)k.lds_max_n && max_n <= 65535 &&
+                 lds_state_bytes(max_n) + scratch_bytes(p.wg) <= (size_t)di.lds_per_block;
+    p.dyn_lds = p.lds_path ? lds_state_bytes(max_n) : 0;
+    int per_cu = occupancy_blocks(p.lds_path, p.wg, p.dyn_lds);
+    if (per_cu < 1) {
+        BC_REQUIRE(!p.lds_path, BC_E_HIP, "kernel does not fit on a compute unit");
+        p.lds_path = false;
+        p.dyn_lds = 0;
+        per_cu = occupancy_blocks(false, p.wg, 0);
+        BC_REQUIRE(per_cu >= 1, BC_E_HIP, "kernel does not fit on a compute unit");
+    }
+    long grid = (long)per_cu * di.cus;
+    if (k.teams > 0) grid = std::min<long>(grid, k.teams);
+    grid = std::min<long>(grid, std::max<uint32_t>(items, 1));
+    p.grid = (unsigned)std::max<long>(grid, 1);
+    p.args.hub = k.hub < 0 ? 0xffffffffu : (uint32_t)std::max(k.hub, 1);
+    p.args.tpv_max = 4;
+    p.args.lds_n = p.lds_path ? max_n : 0;
+    p.args.zero_outputs = 1;
+    return p;
+}
+
+// ---------------------------------------------------------------------------------------
+// single-graph entry (exact / sampled / inspection)
+// ---------------------------------------------------------------------------------------
+struct GraphScratch {
+    SlotPool pool;
+    WorkDesc* desc = nullptr;   // device, one descriptor
+};
+
+static GraphScratch& scratch_of(Graph& g) {
+    if (!g.slots) g.slots = new GraphScratch();
+    return *reinterpret_cast<GraphScratch*>(g.slots);
+}
+
+void graph_scratch_free(Graph& g) {
+    if (!g.slots) return;
+    GraphScratch* s = reinterpret_cast<GraphScratch*>(g.slots);
+    pool_free(s->pool);
+    if (s->desc) (void)hipFree(s->desc);
+    delete s;
+    g.slots = nullptr;
+}
+
+int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
+    GraphScratch& gs = scratch_of(g);
+    if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
+    if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
+    WorkDesc d{};
+    d.row_ptr = g.row_ptr;
+    d.col = g.col;
+    d.bc = ra.bc;
+    d.sources = ra.sources;
+    d.counters = nullptr;
+    d.n = g.n;
+    d.item_begin = 0;
+    d.num_items = ra.num_items;
+    BC_HIP_TRY(hipMemcpyAsync(gs.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
+
+    LaunchPlan p = make_plan(k, (uint32_t)g.n, ra.num_items, g.device);
+    if (!p.lds_path) {
+        pool_ensure(gs.pool, (uint32_t)g.n, (int)p.grid, st);
+        p.args.rec = gs.pool.rec;
+        p.args.queue = gs.pool.queue;
+        p.args.lvl = gs.pool.lvl;
+        p.args.slot_n = gs.pool.slot_n;
+    }
+    p.args.descs = gs.desc;
+    p.args.ndesc = 1;
+    p.args.total_items = ra.num_items;
+    p.args.stats = g.stats;
+    p.args.ex_dist = ra.ex_dist;
+    p.args.ex_sigma = ra.ex_sigma;
+    p.args.ex_sigma_f = ra.ex_sigma_f;
+    p.args.ex_delta = ra.ex_delta;
+    enqueue_plan(p, st, (uint32_t)g.n);
+    return p.lds_path ? 1 : 0;
+}
+
+void read_stats(Graph& g, hipStream_t st, CallStats* out) {
+    BC_HIP_TRY(hipMemcpyAsync(out, g.stats, sizeof(CallStats), hipMemcpyDeviceToHost, st));
+    BC_HIP_TRY(hipStreamSynchronize(st));
+}
+
+
+// ---------------------------------------------------------------------------------------
+// batch of independent graphs: one work list over every (graph, source) pair, largest graphs
+// first; graphs that fit the LDS-resident path share one persistent launch, larger ones a
+// second one over global-memory slots.  The whole sequence (zeroing, searches) is captured
+// once into a hipGraph and replayed while the same graphs and outputs come back.
+// ---------------------------------------------------------------------------------------
+struct BatchPlan {
+    int device = 0;
+    std::vector<const Graph*> graphs;
+    std::vector<double*> outs;
+    Knobs knobs;
+    WorkDesc* d_descs = nullptr;      // [ndesc]
+    uint32_t* d_counters = nullptr;   // [ndesc][4]
+    CallStats* d_stats = nullptr;     // [2] one per launch class
+    SlotPool pool;
+    std::vector<int> order;           // desc index -> graph index
+    std::vector<int> path;            // desc index -> 1 LDS-resident, 0 global slots
+    LaunchPlan lp[2];
+    uint32_t maxn[2] = {0, 0};
+    int nclass = 0;
+    hipGraph_t hg = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    ~BatchPlan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (hg) (void)hipGraphDestroy(hg);
+        if (d_descs) (void)hipFree(d_descs);
+        if (d_counters) (void)hipFree(d_counters);
+        if (d_stats) (void)hipFree(d_stats);
+        pool_free(pool);
+    }
+    bool same(const bc_graph* gs, int num, double* const* bcs, const Knobs& k, int dev) const {
+        if (dev != device || num != (int)graphs.size()) return false;
+        if (k.wg_size != knobs.wg_size || k.hub != knobs.hub || k.lds_max_n != knobs.lds_max_n ||
+            k.teams != knobs.teams || k.use_graph != knobs.use_graph)
+            return false;
+        for (int i = 0; i < num; ++i)
+            if ((const Graph*)gs[i] != graphs[i] || bcs[i] != outs[i]) return false;
+        return true;
+    }
+};
+
+static std::mutex g_batch_mu;
+static BatchPlan* g_batch_plan = nullptr;
+
+static void enqueue_batch(BatchPlan& bp, hipStream_t st) {
+    for (int c = 0; c < bp.nclass; ++c) enqueue_plan(bp.lp[c], st, bp.maxn[c]);
+}
+
+void batch_release_all() {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    delete g_batch_plan;
+    g_batch_plan = nullptr;
+}
+
+static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* bcs, const Knobs& k, int dev,
+                                   hipStream_t st) {
+    BatchPlan* bp = new BatchPlan();
+    try {
+        bp->device = dev;
+        bp->knobs = k;
+        for (int i = 0; i < num; ++i) {
+            bp->graphs.push_back((const Graph*)gs[i]);
+            bp->outs.push_back(bcs[i]);
+        }
+        // class 0: LDS-resident graphs, class 1: the rest; each class largest work first
+        const DevInfo& di = dev_info(dev);
+        const int wg = norm_wg(k.wg_size);
+        auto fits_lds = [&](const Graph* g) {
+            return k.lds_max_n > 0 && g->n <= k.lds_max_n && g->n <= 65535 &&
+                   lds_state_bytes((uint32_t)g->n) + scratch_bytes(wg) <= (size_t)di.lds_per_block;
+        };
+        std::vector<int> cls[2];
+        for (int i = 0; i < num; ++i) cls[fits_lds(bp->graphs[i]) ? 0 : 1].push_back(i);
+        for (auto& v : cls)
+            std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+                const double wa = (double)bp->graphs[a]->n * (bp->graphs[a]->m + 1);
+                const double wb = (double)bp->graphs[b]->n * (bp->graphs[b]->m + 1);
+                return wa > wb;
+            });
+        std::vector<WorkDesc> h(num);
+        BC_HIP_TRY(hipMalloc((void**)&bp->d_descs, sizeof(WorkDesc) * std::max(num, 1)));
+        BC_HIP_TRY(hipMalloc((void**)&bp->d_counters, sizeof(uint32_t) * 4 * std::max(num, 1)));
+        BC_HIP_TRY(hipMalloc((void**)&bp->d_stats, sizeof(CallStats) * 2));
+        int pos = 0;
+        for (int c = 0; c < 2; ++c) {
+            if (cls[c].empty()) continue;
+            const int first = pos;
+            uint32_t items = 0, maxn = 0;
+            for (int gi : cls[c]) {
+                const Graph* g = bp->graphs[gi];
+                WorkDesc& d = h[pos];
+                d = WorkDesc{};
+                d.row_ptr = g->row_ptr;
+                d.col = g->col;
+                d.bc = bp->outs[gi];
+                d.sources = nullptr;
+                d.counters = bp->d_counters + 4 * pos;
+                d.n = g->n;
+                d.item_begin = items;
+                d.num_items = (uint32_t)g->n;
+                items += (uint32_t)g->n;
+                maxn = std::max(maxn, (uint32_t)g->n);
+                bp->order.push_back(gi);
+                ++pos;
+            }
+            const size_t mark = bp->path.size();
+            Knobs kc = k;
+            if (c == 1) kc.lds_max_n = -1;
+            LaunchPlan lp = make_plan(kc, maxn, items, dev);
+            if (!lp.lds_path) {
+                pool_ensure(bp->pool, maxn, (int)lp.grid, st);
+                lp.args.rec = bp->pool.rec;
+                lp.args.queue = bp->pool.queue;
+                lp.args.lvl = bp->pool.lvl;
+                lp.args.slot_n = bp->pool.slot_n;
+            }
+            lp.args.descs = bp->d_descs + first;
+            lp.args.ndesc = (uint32_t)(pos - first);
+            lp.args.total_items = items;
+            lp.args.stats = bp->d_stats + bp->nclass;
+            bp->path.resize(pos, lp.lds_path ? 1 : 0);
+            (void)mark;
+            bp->lp[bp->nclass] = lp;
+            bp->maxn[bp->nclass] = maxn;
+            bp->nclass++;
+        }
+        BC_HIP_TRY(hipMemcpyAsync(bp->d_descs, h.data(), sizeof(WorkDesc) * num, hipMemcpyHostToDevice, st));
+        BC_HIP_TRY(hipStreamSynchronize(st));
+        if (k.use_graph) {
+            hipStream_t cs;
+            BC_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                try {
+                    enqueue_batch(*bp, cs);
+                } catch (...) {
+                    hipGraph_t tmp;
+                    (void)hipStreamEndCapture(cs, &tmp);
+                    if (tmp) (void)hipGraphDestroy(tmp);
+                    (void)hipStreamDestroy(cs);
+                    throw;
+                }
+                e = hipStreamEndCapture(cs, &bp->hg);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&bp->exec, bp->hg, nullptr, nullptr, 0);
+            (void)hipStreamDestroy(cs);
+            BC_HIP_TRY(e);
+        }
+    } catch (...) {
+        delete bp;
+        throw;
+    }
+    return bp;
+}
+
+void run_batch(const bc_graph* gs, int num, double* const* bcs, const Knobs& k, hipStream_t st, bc_info* infos,
+               double* kernel_ms) {
+    int dev = 0;
+    BC_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    if (!g_batch_plan || !g_batch_plan->same(gs, num, bcs, k, dev)) {
+        delete g_batch_plan;
+        g_batch_plan = nullptr;
+        g_batch_plan = build_batch_plan(gs, num, bcs, k, dev, st);
+    }
+    BatchPlan& bp = *g_batch_plan;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (infos) {
+        BC_HIP_TRY(hipEventCreate(&e0));
+        BC_HIP_TRY(hipEventCreate(&e1));
+        BC_HIP_TRY(hipEventRecord(e0, st));
+    }
+    if (bp.exec) BC_HIP_TRY(hipGraphLaunch(bp.exec, st));
+    else enqueue_batch(bp, st);
+    if (infos) {
+        BC_HIP_TRY(hipEventRecord(e1, st));
+        BC_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        BC_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        std::vector<uint32_t> cnt(4 * (size_t)num);
+        BC_HIP_TRY(hipMemcpy(cnt.data(), bp.d_counters, sizeof(uint32_t) * 4 * num, hipMemcpyDeviceToHost));
+        for (int p = 0; p < num; ++p) {
+            const int gi = bp.order[p];
+            bc_info& inf = infos[gi];
+            inf = bc_info{};
+            inf.n_sources = cnt[4 * p + 0];
+            inf.n_sigma_fp64_fallback = cnt[4 * p + 1];
+            inf.levels_max = cnt[4 * p + 2];
+            inf.path = (uint32_t)bp.path[p];
+            inf.kernel_ms = ms;
+            BC_REQUIRE(inf.n_sources == (uint32_t)bp.graphs[gi]->n, BC_E_HIP, "not every source completed");
+        }
+        if (kernel_ms) *kernel_ms = ms;
+    }
+}
+
+}  // namespace bcmi

@@ -1,0 +1,332 @@
+// CSR / CSC construction on the device from an edge list (section II-D: the pair arrays
+// A[i] = u, B[i] = v, converted to the adjacency-list form P/Q with n+1 row offsets).
+//
+// Steps, all on the device:
+//   1. pack   : drop self-loops, flag ids >= n, pack the kept pairs as 64-bit keys u<<b | v
+//   2. sort   : least-significant-digit radix sort of the keys, 8-bit digits
+//   3. unique : flag first occurrences, exclusive scan -> positions; successor ids to col[],
+//               out-degree histogram
+//   4. scan   : exclusive scan of the out-degrees -> row_ptr (n+1 entries)
+//   5. CSC    : keys v<<b | u of the unique edges, sorted again, giving in-neighbour lists
+#include "bc_internal.h"
+
+#include <algorithm>
+
+namespace bcmi {
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanIpt = 8;
+constexpr int kScanTile = kScanBlock * kScanIpt;
+
+constexpr int kRsBlock = 256;
+constexpr int kRsIpt = 16;
+constexpr int kRsTile = kRsBlock * kRsIpt;
+constexpr int kRsWaves = kRsBlock / 64;
+
+__device__ __forceinline__ unsigned lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// inclusive scan across the 64 lanes of a wavefront
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const unsigned lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (unsigned)d) x += y;
+    }
+    return x;
+}
+
+// exclusive scan across the block; returns the block total in *total
+__device__ uint32_t block_excl_scan(uint32_t x, uint32_t* total) {
+    __shared__ uint32_t wsum[kScanBlock / 64];
+    const unsigned lane = lane_id();
+    const unsigned w = threadIdx.x / 64;
+    uint32_t incl = wave_incl_scan(x);
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (unsigned i = 0; i < blockDim.x / 64; ++i) {
+        if (i < w) before += wsum[i];
+        all += wsum[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - x;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_tile(const uint32_t* in, uint32_t* out, uint64_t N,
+                                                          uint32_t* partials) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanIpt;
+    uint32_t v[kScanIpt];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanIpt; ++i) {
+        v[i] = (base + i < N) ? in[base + i] : 0u;
+        sum += v[i];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(sum, &total);
+#pragma unroll
+    for (int i = 0; i < kScanIpt; ++i) {
+        if (base + i < N) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0 && partials) partials[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_add(uint32_t* out, uint64_t N, const uint32_t* offs) {
+    const uint32_t add = offs[blockIdx.x];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    for (int i = threadIdx.x; i < kScanTile; i += kScanBlock)
+        if (base + i < N) out[base + i] += add;
+}
+
+// exclusive scan of N uint32 values (in and out may alias)
+void scan_u32(const uint32_t* in, uint32_t* out, uint64_t N, hipStream_t st) {
+    if (N == 0) return;
+    const uint64_t G = (N + kScanTile - 1) / kScanTile;
+    if (G == 1) {
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kScanBlock), 0, st, in, out, N, nullptr);
+        BC_HIP_TRY(hipGetLastError());
+        return;
+    }
+    uint32_t* part = nullptr;
+    BC_HIP_TRY(hipMallocAsync((void**)&part, G * sizeof(uint32_t), st));
+    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)G), dim3(kScanBlock), 0, st, in, out, N, part);
+    BC_HIP_TRY(hipGetLastError());
+    scan_u32(part, part, G, st);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)G), dim3(kScanBlock), 0, st, out, N, part);
+    BC_HIP_TRY(hipGetLastError());
+    BC_HIP_TRY(hipFreeAsync(part, st));
+}
+
+// --- 1. pack ------------------------------------------------------------------------------
+__global__ void k_pack(const uint32_t* src, const uint32_t* dst, uint64_t M, uint32_t n, int vbits,
+                       uint64_t* keys, uint32_t* counters /* [0] kept, [1] bad id */) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool keep = false;
+    uint64_t key = 0;
+    if (i < M) {
+        const uint32_t u = src[i], v = dst[i];
+        if (u >= n || v >= n) {
+            atomicOr(&counters[1], 1u);
+        } else if (u != v) {
+            keep = true;
+            key = ((uint64_t)u << vbits) | v;
+        }
+    }
+    const uint64_t mask = __ballot(keep);
+    if (mask == 0) return;
+    const unsigned lane = lane_id();
+    const unsigned leader = __builtin_ctzll(mask);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&counters[0], (uint32_t)__builtin_popcountll(mask));
+    base = __shfl(base, leader, 64);
+    if (keep) keys[base + __builtin_popcountll(mask & ((1ull << lane) - 1))] = key;
+}
+
+// --- 2. radix sort --------------------------------------------------------------------------
+__global__ void __launch_bounds__(kRsBlock) k_rs_hist(const uint64_t* keys, uint64_t N, int shift, uint32_t* hist,
+                                                      uint32_t G) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+    for (int i = threadIdx.x; i < kRsTile; i += kRsBlock) {
+        const uint64_t idx = base + i;
+        if (idx < N) atomicAdd(&h[(keys[idx] >> shift) & 0xff], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: keys of one tile are placed in input order within each digit.
+__global__ void __launch_bounds__(kRsBlock) k_rs_scatter(const uint64_t* in, uint64_t* out, uint64_t N, int shift,
+                                                         const uint32_t* offs, uint32_t G) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kRsWaves][256];
+    const unsigned lane = lane_id();
+    const unsigned w = threadIdx.x / 64;
+    run[threadIdx.x] = offs[(uint64_t)threadIdx.x * G + blockIdx.x];
+    const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsIpt; ++r) {
+#pragma unroll
+        for (int q = 0; q < kRsWaves; ++q) wcnt[q][threadIdx.x] = 0;
+        __syncthreads();
+        const uint64_t idx = base + (uint64_t)r * kRsBlock + threadIdx.x;
+        const bool valid = idx < N;
+        const uint64_t key = valid ? in[idx] : 0;
+        const uint32_t digit = (uint32_t)(key >> shift) & 0xff;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t ones = __ballot(valid && ((digit >> b) & 1));
+            peers &= ((digit >> b) & 1) ? ones : ~ones;
+        }
+        const uint32_t rank = __builtin_popcountll(peers & ((1ull << lane) - 1));
+        if (valid && rank == 0) wcnt[w][digit] = __builtin_popcountll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[digit] + rank;
+            for (unsigned q = 0; q < w; ++q) pos += wcnt[q][digit];
+            out[pos] = key;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int q = 0; q < kRsWaves; ++q) add += wcnt[q][threadIdx.x];
+        run[threadIdx.x] += add;
+    }
+}
+
+// sorts keys[0..N) on bits [0, bits); result returned in whichever buffer holds it
+uint64_t* radix_sort(uint64_t* keys, uint64_t* tmp, uint64_t N, int bits, hipStream_t st) {
+    if (N <= 1) return keys;
+    const uint32_t G = (uint32_t)((N + kRsTile - 1) / kRsTile);
+    uint32_t* hist = nullptr;
+    BC_HIP_TRY(hipMallocAsync((void**)&hist, (size_t)256 * G * sizeof(uint32_t), st));
+    uint64_t* a = keys;
+    uint64_t* b = tmp;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(G), dim3(kRsBlock), 0, st, a, N, shift, hist, G);
+        BC_HIP_TRY(hipGetLastError());
+        scan_u32(hist, hist, (uint64_t)256 * G, st);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(G), dim3(kRsBlock), 0, st, a, b, N, shift, hist, G);
+        BC_HIP_TRY(hipGetLastError());
+        std::swap(a, b);
+    }
+    BC_HIP_TRY(hipFreeAsync(hist, st));
+    return a;
+}
+
+// --- 3. unique ------------------------------------------------------------------------------
+__global__ void k_first_flags(const uint64_t* keys, uint64_t N, uint32_t* flags) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+__global__ void k_unique_scatter(const uint64_t* keys, uint64_t N, const uint32_t* flags, const uint32_t* pos,
+                                 int vbits, uint64_t* ukeys, uint32_t* col, uint32_t* deg) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N && flags[i]) {
+        const uint64_t k = keys[i];
+        const uint32_t u = (uint32_t)(k >> vbits);
+        const uint32_t v = (uint32_t)(k & ((1ull << vbits) - 1));
+        ukeys[pos[i]] = ((uint64_t)v << vbits) | u;   // transposed key, for the CSC sort
+        col[pos[i]] = v;
+        atomicAdd(&deg[u], 1u);
+    }
+}
+
+// --- 5. CSC ---------------------------------------------------------------------------------
+__global__ void k_csc_fill(const uint64_t* tkeys, uint64_t N, int vbits, uint32_t* row, uint32_t* indeg) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) {
+        const uint64_t k = tkeys[i];
+        row[i] = (uint32_t)(k & ((1ull << vbits) - 1));
+        atomicAdd(&indeg[(uint32_t)(k >> vbits)], 1u);
+    }
+}
+
+__global__ void k_max_u32(const uint32_t* x, uint64_t N, uint32_t* out) {
+    uint32_t best = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+        best = max(best, x[i]);
+    for (int d = 32; d > 0; d >>= 1) best = max(best, (uint32_t)__shfl_xor(best, d, 64));
+    if (lane_id() == 0) atomicMax(out, best);
+}
+
+inline unsigned grid_for(uint64_t N, int block) { return (unsigned)std::max<uint64_t>(1, (N + block - 1) / block); }
+
+}  // namespace
+
+void build_csr_device(int32_t n, int64_t m_in, const uint32_t* d_src, const uint32_t* d_dst, hipStream_t st,
+                      Graph& g) {
+    BC_REQUIRE(n >= 1, BC_E_RANGE, "n must be >= 1");
+    BC_REQUIRE(m_in >= 0, BC_E_INVAL, "m_in must be >= 0");
+    BC_REQUIRE(m_in < (int64_t)0xffffffffLL, BC_E_RANGE, "more than 2^32-2 input pairs");
+    BC_REQUIRE(m_in == 0 || (d_src && d_dst), BC_E_INVAL, "null edge arrays");
+    const uint64_t M = (uint64_t)m_in;
+    int vbits = 1;
+    while (vbits < 31 && (1ull << vbits) < (uint64_t)n) ++vbits;
+
+    g.n = n;
+    BC_HIP_TRY(hipMalloc((void**)&g.row_ptr, sizeof(uint32_t) * (n + 1)));
+    BC_HIP_TRY(hipMalloc((void**)&g.csc_ptr, sizeof(uint32_t) * (n + 1)));
+    BC_HIP_TRY(hipMemsetAsync(g.row_ptr, 0, sizeof(uint32_t) * (n + 1), st));
+    BC_HIP_TRY(hipMemsetAsync(g.csc_ptr, 0, sizeof(uint32_t) * (n + 1), st));
+
+    uint32_t* counters = nullptr;   // [0] kept pairs, [1] bad id, [2] unique edges, [3] max degree
+    BC_HIP_TRY(hipMallocAsync((void**)&counters, 4 * sizeof(uint32_t), st));
+    BC_HIP_TRY(hipMemsetAsync(counters, 0, 4 * sizeof(uint32_t), st));
+    uint32_t h[4] = {0, 0, 0, 0};
+
+    uint64_t *keys = nullptr, *tmp = nullptr;
+    if (M > 0) {
+        BC_HIP_TRY(hipMallocAsync((void**)&keys, M * sizeof(uint64_t), st));
+        BC_HIP_TRY(hipMallocAsync((void**)&tmp, M * sizeof(uint64_t), st));
+        hipLaunchKernelGGL(k_pack, dim3(grid_for(M, 256)), dim3(256), 0, st, d_src, d_dst, M, (uint32_t)n, vbits,
+                           keys, counters);
+        BC_HIP_TRY(hipGetLastError());
+        BC_HIP_TRY(hipMemcpyAsync(h, counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        BC_HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (h[1]) {
+        (void)hipFreeAsync(keys, st);
+        (void)hipFreeAsync(tmp, st);
+        (void)hipFreeAsync(counters, st);
+        (void)hipStreamSynchronize(st);
+        throw Error{BC_E_RANGE, "edge list holds a vertex id >= n"};
+    }
+    const uint64_t K = h[0];
+    uint32_t m = 0;
+    if (K > 0) {
+        uint64_t* sorted = radix_sort(keys, tmp, K, 2 * vbits, st);
+        uint64_t* other = (sorted == keys) ? tmp : keys;
+        uint32_t *flags = nullptr, *pos = nullptr;
+        BC_HIP_TRY(hipMallocAsync((void**)&flags, K * sizeof(uint32_t), st));
+        BC_HIP_TRY(hipMallocAsync((void**)&pos, K * sizeof(uint32_t), st));
+        hipLaunchKernelGGL(k_first_flags, dim3(grid_for(K, 256)), dim3(256), 0, st, sorted, K, flags);
+        BC_HIP_TRY(hipGetLastError());
+        scan_u32(flags, pos, K, st);
+        uint32_t last[2];
+        BC_HIP_TRY(hipMemcpyAsync(&last[0], pos + K - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        BC_HIP_TRY(hipMemcpyAsync(&last[1], flags + K - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        BC_HIP_TRY(hipStreamSynchronize(st));
+        m = last[0] + last[1];
+        BC_HIP_TRY(hipMalloc((void**)&g.col, sizeof(uint32_t) * std::max<uint32_t>(m, 1)));
+        BC_HIP_TRY(hipMalloc((void**)&g.csc_row, sizeof(uint32_t) * std::max<uint32_t>(m, 1)));
+        // out-degrees are counted into row_ptr[0..n), then scanned in place (row_ptr[n] = 0
+        // before the scan, m after it)
+        hipLaunchKernelGGL(k_unique_scatter, dim3(grid_for(K, 256)), dim3(256), 0, st, sorted, K, flags, pos, vbits,
+                           other, g.col, g.row_ptr);
+        BC_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_max_u32, dim3(std::min<unsigned>(grid_for(n, 256), 1024)), dim3(256), 0, st, g.row_ptr,
+                           (uint64_t)n, counters + 3);
+        BC_HIP_TRY(hipGetLastError());
+        scan_u32(g.row_ptr, g.row_ptr, (uint64_t)n + 1, st);
+        // CSC: sort the transposed keys of the unique edges
+        uint64_t* tsorted = radix_sort(other, sorted, m, 2 * vbits, st);
+        hipLaunchKernelGGL(k_csc_fill, dim3(grid_for(m, 256)), dim3(256), 0, st, tsorted, (uint64_t)m, vbits,
+                           g.csc_row, g.csc_ptr);
+        BC_HIP_TRY(hipGetLastError());
+        scan_u32(g.csc_ptr, g.csc_ptr, (uint64_t)n + 1, st);
+        BC_HIP_TRY(hipFreeAsync(flags, st));
+        BC_HIP_TRY(hipFreeAsync(pos, st));
+        BC_HIP_TRY(hipMemcpyAsync(&h[3], counters + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    } else {
+        BC_HIP_TRY(hipMalloc((void**)&g.col, sizeof(uint32_t)));
+        BC_HIP_TRY(hipMalloc((void**)&g.csc_row, sizeof(uint32_t)));
+    }
+    if (keys) BC_HIP_TRY(hipFreeAsync(keys, st));
+    if (tmp) BC_HIP_TRY(hipFreeAsync(tmp, st));
+    BC_HIP_TRY(hipFreeAsync(counters, st));
+    BC_HIP_TRY(hipStreamSynchronize(st));
+    g.m = m;
+    g.max_out_degree = h[3];
+}
+
+}  // namespace bcmi

@@ -1,0 +1,337 @@
+"""Device path vs the CPU oracle, element by element, through the C ABI (GPU only).
+
+Distances, path counts and the overflowing-source set must match bit for bit; dependencies
+and BC within 1e-9 relative, with structural zeros exact.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_7764_amd import graphgen as gg
+
+from helpers import certificate, rel_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bc():
+    import torch
+    from paper_1409_7764_amd import bcmi
+    assert torch.cuda.is_available()
+    bcmi.lib()
+    return bcmi
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def np_of(t):
+    return t.detach().cpu().numpy()
+
+
+# ---------------------------------------------------------------------------------------
+# a1: CSR / CSC builder
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["rmat10", "random_loops_dups", "single_vertex", "empty", "grid", "path"])
+def test_csr_build_bit_exact(bc, case):
+    say("csr case", case)
+    if case == "rmat10":
+        n, u, v = gg.rmat(10, 8, 10)
+    elif case == "random_loops_dups":
+        n, u, v = gg.random_digraph(3001, 40000, 7)
+    elif case == "single_vertex":
+        n, u, v = 1, np.array([0, 0], np.uint32), np.array([0, 0], np.uint32)
+    elif case == "empty":
+        n, u, v = 17, np.zeros(0, np.uint32), np.zeros(0, np.uint32)
+    elif case == "grid":
+        n, u, v = gg.grid_random_orientation(40, 37, 1)
+    else:
+        n, u, v = gg.directed_path(1000)
+    g = bc.bc_build_csr(n, u, v)
+    rp, col, cp, cr = g.arrays()
+    o = oracle.Graph(n, u, v)
+    assert g.n == n and g.m == o.m
+    assert np.array_equal(rp.numpy(), o.row_ptr.astype(np.int64))
+    assert np.array_equal(col.numpy(), o.col.astype(np.int64))
+    # CSC: in-neighbour lists sorted by (target, source)
+    src = np.repeat(np.arange(n), np.diff(o.row_ptr.astype(np.int64)))
+    order = np.lexsort((src, o.col))
+    assert np.array_equal(cr.numpy(), src[order])
+    assert np.array_equal(cp.numpy(), np.concatenate([[0], np.cumsum(np.bincount(o.col, minlength=n))]))
+    g.free()
+
+
+def test_csr_build_rejects_bad_input(bc):
+    with pytest.raises(bc.BcError) as e:
+        bc.bc_build_csr(10, np.array([0, 10], np.uint32), np.array([1, 2], np.uint32))
+    assert e.value.code == bc.BC_E_RANGE
+    with pytest.raises(bc.BcError) as e:
+        bc.bc_build_csr(0, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    assert e.value.code == bc.BC_E_RANGE
+
+
+# ---------------------------------------------------------------------------------------
+# a2-a6: one source, bit-exact distances and counts
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("scale,ef,seed", [(10, 8, 10), (12, 16, 3)])
+def test_sssp_bit_exact(bc, scale, ef, seed):
+    n, u, v = gg.rmat(scale, ef, seed)
+    g = bc.bc_build_csr(n, u, v)
+    o = oracle.Graph(n, u, v)
+    outdeg = np.diff(o.row_ptr.astype(np.int64))
+    srcs = [int(np.argmax(outdeg)), 0, 1, int(np.nonzero(outdeg == 0)[0][0]), n - 1]
+    for s in srcs:
+        say("sssp", scale, s)
+        r = bc.bc_sssp(g, s)
+        w = oracle.brandes_source(o, s)
+        assert not r["overflow"] and not w["overflow"]
+        assert np.array_equal(np_of(r["dist"]), w["dist"])
+        assert np.array_equal(np_of(r["sigma_u64"]).view(np.uint64), w["sigma"])
+        rel_close(np_of(r["sigma_f64"]), w["sigma_f"], 0.0, "sigma_f64")
+        rel_close(np_of(r["delta"]), w["delta"], what="delta")
+        certificate(n, o.row_ptr, o.col, s, np_of(r["dist"]), np_of(r["sigma_u64"]).view(np.uint64))
+    g.free()
+
+
+# ---------------------------------------------------------------------------------------
+# exact BC, both state homes, every expansion strategy
+# ---------------------------------------------------------------------------------------
+def test_exact_rmat_scale10_both_paths(bc):
+    n, u, v = gg.rmat(10, 8, 10)
+    g = bc.bc_build_csr(n, u, v)
+    want, ovf, st = oracle.bc(oracle.Graph(n, u, v))
+    for lds in (0, -1):
+        say("exact s10 lds_max_n", lds)
+        got, info = bc.bc_exact(g, tuning=bc.tuning(lds_max_n=lds) if lds else None, info=True)
+        assert info["path"] == (1 if lds == 0 else 0)
+        assert info["n_sources"] == n and info["n_sigma_fp64_fallback"] == 0
+        assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+        rel_close(np_of(got), want, what=f"bc lds={lds}")
+    g.free()
+
+
+@pytest.mark.parametrize("wg", [64, 256, 1024])
+@pytest.mark.parametrize("hub", [1, 16, -1])
+@pytest.mark.parametrize("lds", [4096, -1])
+def test_strategies_agree(bc, wg, hub, lds):
+    n, u, v = gg.rmat(11, 16, 4)
+    key = (n, len(u))
+    if not hasattr(test_strategies_agree, "cache"):
+        test_strategies_agree.cache = {}
+    cache = test_strategies_agree.cache
+    if key not in cache:
+        cache[key] = oracle.bc(oracle.Graph(n, u, v))[0]
+    want = cache[key]
+    say("strategy wg", wg, "hub", hub, "lds", lds)
+    g = bc.bc_build_csr(n, u, v)
+    got, info = bc.bc_exact(g, tuning=bc.tuning(wg_size=wg, hub_threshold=hub, lds_max_n=lds), info=True)
+    assert info["path"] == (1 if lds > 0 else 0)
+    rel_close(np_of(got), want, what=f"wg={wg} hub={hub} lds={lds}")
+    g.free()
+
+
+# ---------------------------------------------------------------------------------------
+# a5: exact uint64 overflow detection and the double-precision recount
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [63, 64, 80])
+def test_overflow_diamond_chain(bc, k):
+    n, u, v = gg.diamond_chain(k)
+    g = bc.bc_build_csr(n, u, v)
+    o = oracle.Graph(n, u, v)
+    say("diamond", k)
+    r = bc.bc_sssp(g, 0)
+    w = oracle.brandes_source(o, 0)
+    assert r["overflow"] == w["overflow"] == (k >= 64)
+    assert np.array_equal(np_of(r["dist"]), w["dist"])
+    if not w["overflow"]:
+        assert np.array_equal(np_of(r["sigma_u64"]).view(np.uint64), w["sigma"])
+    rel_close(np_of(r["sigma_f64"]), w["sigma_f"], 1e-12, "sigma_f64")
+    rel_close(np_of(r["delta"]), w["delta"], what="delta")
+    want, ovf, _ = oracle.bc(o)
+    for lds in (0, -1):
+        got, info = bc.bc_exact(g, tuning=bc.tuning(lds_max_n=lds) if lds else None, info=True)
+        assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
+        rel_close(np_of(got), want, what="bc")
+    g.free()
+
+
+def test_overflow_grid_dag(bc):
+    n, u, v = gg.grid_dag(35, 35)
+    g = bc.bc_build_csr(n, u, v)
+    o = oracle.Graph(n, u, v)
+    want, ovf, _ = oracle.bc(o)
+    assert ovf.sum() >= 1
+    for lds in (0, -1):
+        say("grid dag 35 lds", lds)
+        got, info = bc.bc_exact(g, tuning=bc.tuning(lds_max_n=lds) if lds else None, info=True)
+        assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
+        rel_close(np_of(got), want, what="bc")
+    # the overflowing source set itself, one source at a time
+    for s in [0, 1, 35, 36, 70]:
+        assert bc.bc_sssp(g, s)["overflow"] == bool(oracle.brandes_source(o, s)["overflow"])
+    g.free()
+
+
+def test_high_diameter_lattice(bc):
+    n, u, v = gg.grid_random_orientation(64, 64, 1)
+    g = bc.bc_build_csr(n, u, v)
+    o = oracle.Graph(n, u, v)
+    want, ovf, st = oracle.bc(o)
+    for lds in (0, -1):
+        say("lattice 64x64 lds", lds)
+        got, info = bc.bc_exact(g, tuning=bc.tuning(lds_max_n=lds) if lds else None, info=True)
+        assert info["levels_max"] == int(st[:, 3].max())
+        assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
+        rel_close(np_of(got), want, what="bc")
+    g.free()
+
+
+# ---------------------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------------------
+def test_edge_cases(bc):
+    import torch
+    g = bc.bc_build_csr(1, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    assert np_of(bc.bc_exact(g)).tolist() == [0.0]
+    g.free()
+    g = bc.bc_build_csr(5, np.array([1, 1], np.uint32), np.array([1, 1], np.uint32))   # loops only
+    assert g.m == 0
+    assert np_of(bc.bc_exact(g)).tolist() == [0.0] * 5
+    g.free()
+    n, u, v = gg.directed_path(700)     # deep, one vertex per level
+    g = bc.bc_build_csr(n, u, v)
+    for lds in (0, -1):
+        got = np_of(bc.bc_exact(g, tuning=bc.tuning(lds_max_n=lds) if lds else None))
+        assert got.tolist() == [float(i * (n - 1 - i)) for i in range(n)]
+    out = torch.full((n,), 7.0, dtype=torch.float64, device="cuda")
+    bc.bc_sampled(g, np.zeros(0, np.uint32), out=out)
+    assert np_of(out).tolist() == [0.0] * n
+    with pytest.raises(bc.BcError) as e:
+        bc.bc_sampled(g, np.array([3, n], np.uint32), info=True)
+    assert e.value.code == bc.BC_E_RANGE
+    with pytest.raises(bc.BcError):
+        bc.bc_sssp(g, n)
+    g.free()
+
+
+def test_sampled_multiset_and_linearity(bc):
+    n, u, v = gg.rmat(12, 8, 9)
+    g = bc.bc_build_csr(n, u, v)
+    s1 = gg.uniform_sources(n, 300, 1)
+    s2 = gg.uniform_sources(n, 123, 2)
+    a = np_of(bc.bc_sampled(g, s1))
+    b = np_of(bc.bc_sampled(g, s2))
+    c = np_of(bc.bc_sampled(g, np.concatenate([s1, s2])))
+    d = np_of(bc.bc_sampled(g, np.concatenate([s1, s1])))
+    rel_close(c, a + b, 1e-12)
+    rel_close(d, 2 * a, 1e-12)
+    want, _, _ = oracle.bc(oracle.Graph(n, u, v), np.concatenate([s1, s2]))
+    rel_close(c, want)
+    e = np_of(bc.bc_sampled(g, np.arange(n, dtype=np.uint32)))
+    rel_close(e, np_of(bc.bc_exact(g)), 1e-12)
+    g.free()
+
+
+# ---------------------------------------------------------------------------------------
+# workload-shaped graphs (R-MAT scale 16 and 20, 1024x1024 lattice) in the launch shapes
+# the benchmark uses, checked on source subsets the oracle finishes quickly
+# ---------------------------------------------------------------------------------------
+def test_rmat_scale16_sampled_subset(bc):
+    n, u, v = gg.rmat(16, 16, 16)
+    g = bc.bc_build_csr(n, u, v)
+    S = gg.uniform_sources(n, 256, 1616)
+    say("rmat16 sampled 256")
+    got, info = bc.bc_sampled(g, S, info=True)
+    want, ovf, st = oracle.bc(oracle.Graph(n, u, v), S)
+    assert info["n_sigma_fp64_fallback"] == int(ovf.sum()) == 0
+    # exact work counters: reached vertices, examined edges, DAG edges, deepest level
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    assert info["levels_max"] == int(st[:, 3].max())
+    rel_close(np_of(got), want)
+    g.free()
+
+
+def test_rmat_scale16_exact_properties(bc):
+    """Full exact run in the benchmark's configuration: equals the sum of sampled runs over a
+    partition of the vertex set, has exact zeros where no path can pass (no in- or no
+    out-edges), and a seeded subset matches the oracle."""
+    n, u, v = gg.rmat(16, 16, 16)
+    g = bc.bc_build_csr(n, u, v)
+    say("rmat16 exact")
+    full, info = bc.bc_exact(g, info=True)
+    full = np_of(full)
+    assert info["n_sources"] == n
+    perm = np.random.default_rng(5).permutation(n).astype(np.uint32)
+    acc = np.zeros(n)
+    for part in np.array_split(perm, 3):
+        acc += np_of(bc.bc_sampled(g, part))
+    rel_close(full, acc, 1e-11)
+    o = oracle.Graph(n, u, v)
+    indeg = np.bincount(o.col, minlength=n)
+    outdeg = np.diff(o.row_ptr.astype(np.int64))
+    assert np.all(full[(indeg == 0) | (outdeg == 0)] == 0)
+    assert np.all(full >= 0)
+    g.free()
+
+
+@pytest.mark.slow
+def test_rmat_scale20_sampled_subset(bc):
+    n, u, v = gg.rmat(20, 16, 20)
+    g = bc.bc_build_csr(n, u, v)
+    S = gg.uniform_sources(n, 1024, 2020)
+    say("rmat20 sampled 1024")
+    allk = np_of(bc.bc_sampled(g, S))
+    sub = S[:24]
+    got = np_of(bc.bc_sampled(g, sub))
+    want, _, _ = oracle.bc(oracle.Graph(n, u, v), sub)
+    rel_close(got, want)
+    rest = np_of(bc.bc_sampled(g, S[24:]))
+    rel_close(allk, got + rest, 1e-11)
+    g.free()
+
+
+@pytest.mark.slow
+def test_lattice_1024_sampled_subset(bc):
+    n, u, v = gg.grid_random_orientation(1024, 1024, 1)
+    g = bc.bc_build_csr(n, u, v)
+    S = gg.uniform_sources(n, 48, 1024)
+    say("lattice1024 sampled 48")
+    got, info = bc.bc_sampled(g, S, info=True)
+    want, ovf, _ = oracle.bc(oracle.Graph(n, u, v), S)
+    assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
+    rel_close(np_of(got), want)
+    g.free()
+
+
+# ---------------------------------------------------------------------------------------
+# a8-a9: batch of uneven graphs, one captured launch per class, replayed
+# ---------------------------------------------------------------------------------------
+def test_batch_matches_oracle_and_replays(bc):
+    import torch
+    rng = np.random.default_rng(77)
+    specs = [(int(rng.integers(3, 11)), int(rng.choice([4, 8, 16])), 4096_000 + i) for i in range(40)]
+    specs += [(13, 8, 1), (13, 4, 2)]           # too large for the LDS path
+    graphs, olds = [], []
+    for sc, ef, seed in specs:
+        n, u, v = gg.rmat(sc, ef, seed)
+        graphs.append(bc.bc_build_csr(n, u, v))
+        olds.append(oracle.bc(oracle.Graph(n, u, v))[0])
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in graphs]
+    for rep in range(3):
+        say("batch replay", rep)
+        for o in outs:
+            o.fill_(-1.0)
+        _, infos = bc.bc_batch(graphs, outs, info=True)
+        torch.cuda.synchronize()
+        for i, (o, w) in enumerate(zip(outs, olds)):
+            rel_close(np_of(o), w, what=f"graph {i}")
+            assert infos[i]["n_sources"] == graphs[i].n
+        assert infos[-1]["path"] == 0 and infos[0]["path"] == 1
+        _ = torch.randn(1000, device="cuda").sum().item()   # unrelated eager work between replays
+    for g in graphs:
+        g.free()
