@@ -30,23 +30,31 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic bytes moved by the device design, per reached vertex / examined edge / DAG
-# edge of one source (forward + backward + reset); the derivation is in the design notes.
-BYTES_PER_REACHED = 96
-BYTES_PER_EXAMINED = 16
-BYTES_PER_DAG_EDGE = 24
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(reached, examined, dag):
-    return BYTES_PER_REACHED * reached + BYTES_PER_EXAMINED * examined + BYTES_PER_DAG_EDGE * dag
+def algorithmic_bytes(info):
+    """Bytes the launch's design must move, from its exact work counters.
+
+    One source per workgroup (paths 0, 1): 96 B per reached vertex, 16 B per examined edge,
+    24 B per shortest-path DAG edge, summed over sources.
+    64-source batches (path 2): 168 B per level-list entry, 24 B per out-edge read for an
+    entry (forward + backward), 32 B per reached (vertex, source) pair, 24 B per DAG
+    (edge, source) pair.
+    """
+    if info["path"] == 2:
+        return (168 * info["batch_entries"] + 24 * info["batch_edge_visits"] + 32 * info["reached"]
+                + 24 * info["dag_edges"])
+    return 96 * info["reached"] + 16 * info["examined"] + 24 * info["dag_edges"]
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ["bc_kernels.hip", "bc_internal.h"]:
-        with open(os.path.join(ROOT, "paper_1409_7764_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+    csrc = os.path.join(ROOT, "paper_1409_7764_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -84,16 +92,14 @@ def cpu_baseline(n, u, v, sources, m, budget_s):
     threads = max(1, min(threads, oracle.max_threads() if oracle.max_threads() > 0 else threads))
     g = oracle.Graph(n, u, v)
     k = min(len(sources), max(threads, 16))
-    t0 = time.perf_counter()
-    oracle.bc(g, sources[:k], threads=threads)
-    dt = time.perf_counter() - t0
-    # grow the sample to roughly the time budget
-    k2 = int(min(len(sources), max(k, k * budget_s / max(dt, 1e-3))))
-    if k2 > k:
+    while True:
         t0 = time.perf_counter()
-        oracle.bc(g, sources[:k2], threads=threads)
+        oracle.bc(g, sources[:k], threads=threads)
         dt = time.perf_counter() - t0
-        k = k2
+        if dt >= budget_s / 2 or k >= len(sources):
+            break
+        # grow the sample towards the time budget
+        k = int(min(len(sources), max(2 * k, k * budget_s / max(dt, 1e-3))))
     return {"value": k * m / dt / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
             "sample": f"{k} of the {len(sources)} sources (first {k} in benchmark order), "
                       f"{dt:.1f} s on {threads} threads of {cpu_info()}"}
@@ -127,6 +133,11 @@ def bench_single(args, torch, bcmi, gg):
     if args.tune:
         tune = bcmi.bc_tune(g)
     tun = bcmi.tuning(**{k: v for k, v in (tune or {}).items()}) if tune else None
+    if args.strategy != "auto":
+        force = {"batched": dict(batched=1), "per-source": dict(batched=-1)}[args.strategy]
+        base = dict(tune or {})
+        base.update(force)
+        tun = bcmi.tuning(**base)
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     d_src = torch.from_numpy(sources.view(np.int32)).cuda()
 
@@ -148,7 +159,7 @@ def bench_single(args, torch, bcmi, gg):
     k = len(sources)
     kernel_ms = float(np.mean([i["kernel_ms"] for i in infos]))
     inf = infos[-1]
-    nbytes = algorithmic_bytes(inf["reached"], inf["examined"], inf["dag_edges"])
+    nbytes = algorithmic_bytes(inf)
     achieved = nbytes / (kernel_ms / 1e3) / 1e9
     traffic = load_traffic(cfg["workload"], 1)
     res = {
@@ -158,12 +169,12 @@ def bench_single(args, torch, bcmi, gg):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64 path counts, f64 dependencies and BC",
+        "dtype": "u64+f64",
         "data": "synthetic",
         "config": cfg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_bc_lds" if inf["path"] else "k_bc_global",
+                     "kernel": ["k_bc_global", "k_bc_lds", "k_msb"][inf["path"]],
                      "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": nbytes},
         "extra": {
             "traversed_gteps": inf["examined"] / (ms_per_step / 1e3) / 1e9,
@@ -171,7 +182,8 @@ def bench_single(args, torch, bcmi, gg):
             "sources": k, "reached": inf["reached"], "examined": inf["examined"],
             "dag_edges": inf["dag_edges"], "levels_max": inf["levels_max"],
             "sigma_fp64_fallback_sources": inf["n_sigma_fp64_fallback"],
-            "path": "lds" if inf["path"] else "global", "tuning": tune,
+            "path": ["global", "lds", "batched"][inf["path"]], "tuning": tune,
+            "batch_entries": inf["batch_entries"], "batch_edge_visits": inf["batch_edge_visits"],
             "kernel_ms_all": [i["kernel_ms"] for i in infos],
         },
     }
@@ -208,7 +220,7 @@ def bench_batch(args, torch, bcmi, gg):
     res = {"metric": "GTEPS (sources x edges / s), nominal, batched exact BC", "value": nominal / (ms / 1e3) / 1e9,
            "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "u64 path counts, f64 dependencies and BC", "data": "synthetic",
+           "dtype": "u64+f64", "data": "synthetic",
            "config": {"workload": "batch4096-rmat6to12-ef8", "graphs": 4096,
                       "sum_n": int(sum(g.n for g in graphs)), "sum_m": int(sum(g.m for g in graphs))},
            "extra": {"build_csr_ms_total": build_ms, "kernel_ms": infos[-1][0]["kernel_ms"]}}
@@ -224,6 +236,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat20", "lattice", "batch"])
     ap.add_argument("--tune", action="store_true", help="autotune launch knobs first (untimed)")
+    ap.add_argument("--strategy", default="auto", choices=["auto", "batched", "per-source"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle sample")
     args = ap.parse_args()

@@ -68,18 +68,25 @@ typedef struct {
                                    wavefront rather than one thread; < 0 = never */
     int32_t lds_max_n;          /* largest n run by the LDS-resident path; < 0 = never */
     int32_t use_graph;          /* 1 = replay a captured hipGraph, -1 = plain launches */
+    int32_t batched;            /* 1 = 64 sources per batch (one per wavefront lane),
+                                   -1 = one source per workgroup */
+    int32_t batch_wg_size;      /* workgroup size of the batched kernel: 256, 512, 1024 */
 } bc_tuning;
 
 typedef struct {
     uint32_t n_sources;             /* sources processed */
     uint32_t n_sigma_fp64_fallback; /* sources whose path counts overflowed uint64 */
     uint32_t levels_max;            /* deepest BFS (number of levels) over the sources */
-    uint32_t path;                  /* 0 = global-memory slots, 1 = LDS-resident */
+    uint32_t path;                  /* 0 = one source per workgroup, state in global memory;
+                                       1 = one source per workgroup, state in LDS;
+                                       2 = 64-source batches */
     double kernel_ms;               /* device time of the call (HIP events) */
     double t_submit_ms, t_start_ms, t_done_ms; /* bc_serve_poll only: server clock */
     uint64_t reached;               /* sum over sources of vertices reached (source included) */
     uint64_t examined;              /* sum over sources of out-edges of reached vertices */
     uint64_t dag_edges;             /* sum over sources of shortest-path DAG edges */
+    uint64_t batch_entries;         /* path 2: (vertex, level) entries of the batches' lists */
+    uint64_t batch_edge_visits;     /* path 2: out-edges of those entries */
 } bc_info;
 
 /* Build a graph handle from a pair list (section II-D: edge list A[i]=u, B[i]=v).

@@ -30,7 +30,8 @@ class BcError(RuntimeError):
 class bc_tuning(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("wgs_per_source", ctypes.c_int32),
                 ("sources_per_launch", ctypes.c_int32), ("hub_threshold", ctypes.c_int32),
-                ("lds_max_n", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("lds_max_n", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("batched", ctypes.c_int32),
+                ("batch_wg_size", ctypes.c_int32)]
 
 
 class bc_info(ctypes.Structure):
@@ -38,7 +39,8 @@ class bc_info(ctypes.Structure):
                 ("levels_max", ctypes.c_uint32), ("path", ctypes.c_uint32), ("kernel_ms", ctypes.c_double),
                 ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
                 ("t_done_ms", ctypes.c_double), ("reached", ctypes.c_uint64), ("examined", ctypes.c_uint64),
-                ("dag_edges", ctypes.c_uint64)]
+                ("dag_edges", ctypes.c_uint64), ("batch_entries", ctypes.c_uint64),
+                ("batch_edge_visits", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

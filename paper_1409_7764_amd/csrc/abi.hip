@@ -116,6 +116,8 @@ static void fill_info(Graph& g, hipStream_t st, int path, double ms, uint32_t ex
     out.reached = cs.reached;
     out.examined = cs.examined;
     out.dag_edges = cs.dag_edges;
+    out.batch_entries = cs.entries;
+    out.batch_edge_visits = cs.edge_visits;
     *info = out;
 }
 
@@ -289,6 +291,8 @@ bc_status bc_tune(bc_graph gh, bc_tuning* out) {
         r.hub_threshold = k.hub;
         r.lds_max_n = k.lds_max_n;
         r.use_graph = k.use_graph ? 1 : -1;
+        r.batched = k.batched;
+        r.batch_wg_size = k.batch_wg;
         *out = r;
     });
 }

@@ -59,11 +59,14 @@ struct CallStats {
     uint32_t n_overflow;     // sources recounted in double precision
     uint32_t levels_max;     // deepest search
     uint32_t bad_source;     // sources with id >= n (skipped)
-    uint32_t pad[3];
+    uint32_t work_head2;     // work counter of a follow-up launch in the same call
+    uint32_t pad[2];
     uint64_t reached;        // sum over sources of reached vertices (source included)
     uint64_t examined;       // sum over sources of out-edges of reached vertices
     uint64_t dag_edges;      // sum over sources of shortest-path DAG edges
-    uint64_t pad2;
+    uint64_t entries;        // batched path: (vertex, level) entries of the batches' level lists
+    uint64_t edge_visits;    // batched path: out-edges read per entry (once per sweep)
+    uint64_t pad2[3];
 };
 
 // Launch knobs after defaults / tuning are applied.
@@ -74,6 +77,8 @@ struct Knobs {
     int hub = 32;                // wavefront-per-vertex threshold
     int lds_max_n = 4096;
     bool use_graph = true;
+    int batched = 0;             // 1: 64-source batches, -1: one source per workgroup, 0: auto
+    int batch_wg = 1024;         // workgroup size of the batched kernel
 };
 
 // Graph handle (the opaque bc_graph).
@@ -86,6 +91,8 @@ struct Graph {
     uint32_t* csc_ptr = nullptr;   // n+1
     uint32_t* csc_row = nullptr;   // m
     uint32_t max_out_degree = 0;
+    uint32_t max_in_degree = 0;
+    uint32_t zero_out_degree = 0;  // vertices with no out-edges (sources that reach nothing)
     // per-source scratch, grown on demand and reused between calls
     void* slots = nullptr;
     CallStats* stats = nullptr;    // device

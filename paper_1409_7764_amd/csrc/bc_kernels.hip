@@ -61,6 +61,8 @@ struct LaunchArgs {
     uint32_t slot_n;
     uint32_t lds_n;            // LDS path: vertex capacity
     uint32_t zero_outputs;     // zero each descriptor's BC output and counters first
+    const uint32_t* items_dev; // nullable: number of work items, read on the device
+    uint32_t* head;            // nullable: work counter (default: stats->work_head)
     // export of one source (inspection entry point)
     int32_t* ex_dist;
     uint64_t* ex_sigma;
@@ -555,17 +557,19 @@ __device__ __forceinline__ uint32_t find_desc(const WorkDesc* descs, uint32_t nd
 template <int WG>
 __device__ __forceinline__ bool claim_item(const LaunchArgs& a, Scratch<WG>& L, uint32_t& di, uint32_t& s,
                                            uint32_t n_cap) {
+    const uint32_t total = a.items_dev ? *a.items_dev : a.total_items;
+    uint32_t* head = a.head ? a.head : &a.stats->work_head;
     for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t item = atomicAdd(&a.stats->work_head, 1u);
+            const uint32_t item = atomicAdd(head, 1u);
             L.item = item;
-            L.desc = item < a.total_items ? find_desc(a.descs, a.ndesc, item) : 0u;
+            L.desc = item < total ? find_desc(a.descs, a.ndesc, item) : 0u;
         }
         __syncthreads();
         const uint32_t item = L.item;
         di = L.desc;
         __syncthreads();
-        if (item >= a.total_items) return false;
+        if (item >= total) return false;
         const WorkDesc& D = a.descs[di];
         const uint32_t local = item - D.item_begin;
         s = D.sources ? D.sources[local] : local;
@@ -766,7 +770,7 @@ void enqueue_plan(const LaunchPlan& p, hipStream_t st, uint32_t max_n) {
                            0, st, p.args.ex_dist, p.args.ex_sigma, p.args.ex_sigma_f, p.args.ex_delta, max_n);
         BC_HIP_TRY(hipGetLastError());
     }
-    if (p.args.total_items == 0 || p.grid == 0) return;
+    if ((p.args.total_items == 0 && !p.args.items_dev) || p.grid == 0) return;
     if (p.lds_path) {
         switch (p.wg) {
             case 64: launch_lds<64>(p.args, p.grid, p.dyn_lds, st); break;
@@ -817,9 +821,14 @@ LaunchPlan make_plan(const Knobs& k, uint32_t max_n, uint32_t items, int device)
 // ---------------------------------------------------------------------------------------
 // single-graph entry (exact / sampled / inspection)
 // ---------------------------------------------------------------------------------------
+struct MsbPool;
+void msb_pool_delete(MsbPool* p);
+
 struct GraphScratch {
     SlotPool pool;
-    WorkDesc* desc = nullptr;   // device, one descriptor
+    WorkDesc* desc = nullptr;    // device, one descriptor
+    WorkDesc* rdesc = nullptr;   // device, descriptor of the retry list
+    MsbPool* msb = nullptr;
 };
 
 static GraphScratch& scratch_of(Graph& g) {
@@ -832,12 +841,78 @@ void graph_scratch_free(Graph& g) {
     GraphScratch* s = reinterpret_cast<GraphScratch*>(g.slots);
     pool_free(s->pool);
     if (s->desc) (void)hipFree(s->desc);
+    if (s->rdesc) (void)hipFree(s->rdesc);
+    msb_pool_delete(s->msb);
     delete s;
     g.slots = nullptr;
 }
 
+struct MsbPool;
+MsbPool* msb_pool_new();
+void msb_pool_delete(MsbPool* p);
+void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
+                     int wg, int slots_cap, hipStream_t st,
+                     void (*retry_launch)(void*, const uint32_t*, const uint32_t*, uint32_t, hipStream_t),
+                     void* retry_ctx);
+
+// Per-source launch over a device-resident list whose length is known only on the device
+// (sources the batched kernel handed back).
+struct RetryCtx {
+    Graph* g;
+    GraphScratch* gs;
+    Knobs k;
+    double* bc;
+};
+
+static void retry_launch(void* ctx, const uint32_t* list, const uint32_t* count, uint32_t cap, hipStream_t st) {
+    RetryCtx& c = *reinterpret_cast<RetryCtx*>(ctx);
+    Graph& g = *c.g;
+    Knobs k = c.k;
+    k.lds_max_n = -1;
+    k.teams = 64;
+    LaunchPlan p = make_plan(k, (uint32_t)g.n, cap, g.device);
+    pool_ensure(c.gs->pool, (uint32_t)g.n, (int)p.grid, st);
+    p.args.rec = c.gs->pool.rec;
+    p.args.queue = c.gs->pool.queue;
+    p.args.lvl = c.gs->pool.lvl;
+    p.args.slot_n = c.gs->pool.slot_n;
+    WorkDesc d{};
+    d.row_ptr = g.row_ptr;
+    d.col = g.col;
+    d.bc = c.bc;
+    d.sources = list;
+    d.n = g.n;
+    d.num_items = cap;
+    BC_HIP_TRY(hipMemcpyAsync(c.gs->rdesc, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    p.args.descs = c.gs->rdesc;
+    p.args.ndesc = 1;
+    p.args.total_items = 0;
+    p.args.items_dev = count;
+    p.args.head = &g.stats->work_head2;
+    p.args.stats = g.stats;
+    switch (p.wg) {
+        case 64: launch_global<64>(p.args, p.grid, st); break;
+        case 128: launch_global<128>(p.args, p.grid, st); break;
+        case 256: launch_global<256>(p.args, p.grid, st); break;
+        case 512: launch_global<512>(p.args, p.grid, st); break;
+        default: launch_global<1024>(p.args, p.grid, st); break;
+    }
+    BC_HIP_TRY(hipGetLastError());
+}
+
+int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g);
+
+static bool want_batched(const Knobs& k, const Graph& g, uint32_t items) {
+    if (k.batched < 0) return false;
+    const bool lds_ok = k.lds_max_n > 0 && g.n <= k.lds_max_n;
+    if (k.batched > 0) return true;
+    return !lds_ok && items >= 64;
+}
+
 int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     GraphScratch& gs = scratch_of(g);
+    const bool exporting = ra.ex_dist || ra.ex_sigma || ra.ex_sigma_f || ra.ex_delta;
+    if (!exporting && want_batched(k, g, ra.num_items)) return run_batched(ra, k, st, g);
     if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
     if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
     WorkDesc d{};
@@ -869,6 +944,33 @@ int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     p.args.ex_delta = ra.ex_delta;
     enqueue_plan(p, st, (uint32_t)g.n);
     return p.lds_path ? 1 : 0;
+}
+
+int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
+    GraphScratch& gs = scratch_of(g);
+    if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
+    if (!gs.rdesc) BC_HIP_TRY(hipMalloc((void**)&gs.rdesc, sizeof(WorkDesc)));
+    if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
+    if (!gs.msb) gs.msb = msb_pool_new();
+    WorkDesc d{};
+    d.row_ptr = g.row_ptr;
+    d.col = g.col;
+    d.bc = ra.bc;
+    d.n = g.n;
+    d.num_items = ra.num_items;
+    BC_HIP_TRY(hipMemcpyAsync(gs.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    // zero BC and the call counters
+    LaunchPlan z;
+    z.args.descs = gs.desc;
+    z.args.ndesc = 1;
+    z.args.total_items = 0;
+    z.args.stats = g.stats;
+    z.args.zero_outputs = 1;
+    z.grid = 0;
+    enqueue_plan(z, st, (uint32_t)g.n);
+    RetryCtx rc{&g, &gs, k, ra.bc};
+    run_msb_enqueue(*gs.msb, g, ra.sources, ra.num_items, ra.bc, g.stats, k.batch_wg, k.teams, st, retry_launch, &rc);
+    return 2;
 }
 
 void read_stats(Graph& g, hipStream_t st, CallStats* out) {

@@ -239,6 +239,15 @@ __global__ void k_max_u32(const uint32_t* x, uint64_t N, uint32_t* out) {
     if (lane_id() == 0) atomicMax(out, best);
 }
 
+// vertices with no out-edges (row_ptr still holds out-degrees)
+__global__ void k_count_zero(const uint32_t* deg, uint64_t N, uint32_t* out) {
+    uint32_t c = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+        c += deg[i] == 0 ? 1u : 0u;
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (lane_id() == 0 && c) atomicAdd(out, c);
+}
+
 inline unsigned grid_for(uint64_t N, int block) { return (unsigned)std::max<uint64_t>(1, (N + block - 1) / block); }
 
 }  // namespace
@@ -307,17 +316,25 @@ void build_csr_device(int32_t n, int64_t m_in, const uint32_t* d_src, const uint
         hipLaunchKernelGGL(k_max_u32, dim3(std::min<unsigned>(grid_for(n, 256), 1024)), dim3(256), 0, st, g.row_ptr,
                            (uint64_t)n, counters + 3);
         BC_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_count_zero, dim3(std::min<unsigned>(grid_for(n, 256), 1024)), dim3(256), 0, st, g.row_ptr,
+                           (uint64_t)n, counters + 1);
+        BC_HIP_TRY(hipGetLastError());
         scan_u32(g.row_ptr, g.row_ptr, (uint64_t)n + 1, st);
         // CSC: sort the transposed keys of the unique edges
         uint64_t* tsorted = radix_sort(other, sorted, m, 2 * vbits, st);
         hipLaunchKernelGGL(k_csc_fill, dim3(grid_for(m, 256)), dim3(256), 0, st, tsorted, (uint64_t)m, vbits,
                            g.csc_row, g.csc_ptr);
         BC_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_max_u32, dim3(std::min<unsigned>(grid_for(n, 256), 1024)), dim3(256), 0, st, g.csc_ptr,
+                           (uint64_t)n, counters + 2);
+        BC_HIP_TRY(hipGetLastError());
         scan_u32(g.csc_ptr, g.csc_ptr, (uint64_t)n + 1, st);
         BC_HIP_TRY(hipFreeAsync(flags, st));
         BC_HIP_TRY(hipFreeAsync(pos, st));
-        BC_HIP_TRY(hipMemcpyAsync(&h[3], counters + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        BC_HIP_TRY(hipMemcpyAsync(&h[1], counters + 1, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     } else {
+        h[1] = (uint32_t)n;   // every vertex has out-degree 0
+        h[2] = 0;
         BC_HIP_TRY(hipMalloc((void**)&g.col, sizeof(uint32_t)));
         BC_HIP_TRY(hipMalloc((void**)&g.csc_row, sizeof(uint32_t)));
     }
@@ -327,6 +344,8 @@ void build_csr_device(int32_t n, int64_t m_in, const uint32_t* d_src, const uint
     BC_HIP_TRY(hipStreamSynchronize(st));
     g.m = m;
     g.max_out_degree = h[3];
+    g.max_in_degree = h[2];
+    g.zero_out_degree = h[1];
 }
 
 }  // namespace bcmi

@@ -1,0 +1,688 @@
+// Brandes betweenness centrality with 64 sources per batch, one source per wavefront lane.
+//
+// The forward and backward sweeps of section I's method are run for a batch of up to 64
+// sources at once.  A vertex v enters the level-d list of the batch once, with the bit mask
+// of the batch's sources for which d(s, v) = d; an out-edge of v is therefore read once per
+// level for all of those sources.  Per-(vertex, source) state lives in 64-wide rows, so the
+// per-source updates of one edge are one coalesced row access instead of 64 scattered ones:
+//   seen[v]     sources that reached v at a level <= d         (64-bit mask)
+//   nxt[v]      sources reaching v at level d+1 (forward); the level-(d+1) masks, scattered,
+//               during the backward sweep
+//   sig[v][s]   shortest-path count sigma_s(v) (uint64); after v's level has been finished
+//               in the backward sweep, psi_s(v) = (1 + delta_s(v)) / sigma_s(v) (double bits)
+//
+// forward, level d, entry (v, f): for each successor w the lanes of one wavefront test 64
+//   edges at once: dag = f & ~seen[w] are the sources with w at level d+1; they are OR-ed
+//   into nxt[w] (the first writer appends w to the next level's list) and, lane per source,
+//   sig[w][s] += sig[v][s] for s in dag (64-bit integer atomics, issued without waiting for
+//   the old value whenever a bound on sigma proves that no carry can occur; otherwise the
+//   old value is checked and a carry flags that source, which is then recounted exactly by
+//   the per-source kernel in double precision).
+// backward, level d, entry (v, f): succ = f & nxt[w] are the sources with w one level down;
+//   lane s sums psi_s(w), then delta_s(v) = sigma_s(v) * sum, psi_s(v) is stored over
+//   sigma_s(v), and sum over s != v of delta_s(v) is added to BC[v].  Each (v, s) has one
+//   owner lane: no atomics on delta.  A vertex with more than 64 out-edges is split into
+//   pieces; their partial sums meet in a per-batch accumulator row before the owner
+//   finishes the vertex.
+//
+// Sources are grouped by out-degree (a cheap proxy for their distance to the dense core of
+// a scale-free graph), which aligns the batch's levels; sources without out-edges reach no
+// vertex and contribute nothing, so they are not run.
+#include "bc_internal.h"
+
+#include <algorithm>
+
+namespace bcmi {
+
+struct MsbArgs {
+    const uint32_t* row_ptr;
+    const uint32_t* col;
+    double* bc;
+    const uint32_t* plan;        // planned sources, batched in order
+    const uint32_t* plan_count;  // [0]: number of planned sources
+    uint32_t* retry;             // sources handed to the per-source kernel
+    uint32_t* retry_count;
+    CallStats* stats;
+    uint64_t* seen;              // [slots][n]
+    uint64_t* nxt;               // [slots][n]
+    uint64_t* sig;               // [slots][n][64]
+    double* hacc;                // [slots][hub_rows][64]
+    uint32_t* lst_v;             // [slots][cap]
+    uint64_t* lst_m;             // [slots][cap]
+    uint32_t* lvl;               // [slots][max_levels + 2]
+    int32_t n;
+    uint32_t cap;
+    uint32_t max_levels;
+    uint32_t hub_rows;
+    double in2;                  // (largest in-degree)^2
+};
+
+namespace {
+
+constexpr double kSafeSigma = 1.8e19;   // below 2^64 = 1.8447e19
+
+__device__ __forceinline__ unsigned lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ double u2d(uint64_t x) { return __longlong_as_double((long long)x); }
+__device__ __forceinline__ uint64_t d2u(double x) { return (uint64_t)__double_as_longlong(x); }
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int j) {
+    return (uint64_t)__shfl((long long)x, j, 64);
+}
+__device__ __forceinline__ uint64_t wave_max64(uint64_t x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const uint64_t y = (uint64_t)__shfl_xor((long long)x, d, 64);
+        x = x > y ? x : y;
+    }
+    return x;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const unsigned lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (unsigned)d) x += y;
+    }
+    return x;
+}
+__device__ __forceinline__ void level_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <int WG>
+struct MsbLds {
+    uint32_t wsum[WG / 64];
+    uint32_t off[WG];       // unit offsets of the chunk's entries
+    uint32_t ev[WG];        // entry vertex
+    uint64_t em[WG];        // entry source mask
+    uint32_t eb[WG];        // first out-edge
+    uint32_t ed[WG];        // out-degree
+    int32_t eh[WG];         // accumulator row of a split entry, -1 otherwise
+    uint32_t hub_ent[WG];   // accumulator row -> chunk entry
+    uint32_t nhub;
+    uint32_t tail;          // level-list append position
+    uint32_t batch;
+    uint32_t sdeg;          // out-degree sum of the current level
+    uint64_t ovf;           // sources whose counts carried out of 64 bits
+    uint64_t maxsig;        // largest count on the current level
+};
+
+template <int WG>
+__device__ __forceinline__ uint32_t find_owner(const uint32_t* a, uint32_t p) {
+    uint32_t lo = 0, len = WG;
+    while (len > 1) {
+        const uint32_t half = len >> 1;
+        if (a[lo + half] <= p) lo += half;
+        len -= half;
+    }
+    return lo;
+}
+
+template <int WG>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total, uint32_t* wsum) {
+    const unsigned lane = lane_id(), w = threadIdx.x / 64;
+    const uint32_t incl = wave_incl_scan(x);
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < WG / 64; ++i) {
+        const uint32_t t = wsum[i];
+        if (i < (int)w) before += t;
+        all += t;
+    }
+    __syncthreads();
+    total = all;
+    return before + incl - x;
+}
+
+template <int WG>
+__device__ __forceinline__ void append(MsbLds<WG>& L, uint32_t* lv, bool fresh, uint32_t w) {
+    const uint64_t mask = __ballot(fresh);
+    if (mask) {
+        const unsigned lane = lane_id();
+        const unsigned leader = __builtin_ctzll(mask);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&L.tail, (uint32_t)__builtin_popcountll(mask));
+        base = __shfl(base, leader, 64);
+        if (fresh) lv[base + (uint32_t)__builtin_popcountll(mask & ((1ull << lane) - 1ull))] = w;
+    }
+}
+
+// forward work unit: up to 64 out-edges [e0, e1) of the level-d entry (v, f)
+template <int WG>
+__device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, uint64_t* seen, uint64_t* nxt,
+                                         uint64_t* sig, uint32_t* lv, uint32_t v, uint64_t f, uint32_t e0,
+                                         uint32_t e1, bool safe) {
+    const unsigned lane = lane_id();
+    const bool act = (f >> lane) & 1ull;
+    const uint64_t sv = act ? sig[(size_t)v * 64 + lane] : 0ull;
+    const uint64_t mx = wave_max64(sv);
+    if (lane == 0 && mx > L.maxsig) atomicMax((unsigned long long*)&L.maxsig, (unsigned long long)mx);
+    const uint32_t e = e0 + lane;
+    const bool ok = e < e1;
+    uint32_t w = 0;
+    uint64_t dag = 0;
+    bool fresh = false;
+    if (ok) {
+        w = a.col[e];
+        dag = f & ~seen[w];
+        if (dag) fresh = atomicOr((unsigned long long*)&nxt[w], (unsigned long long)dag) == 0ull;
+    }
+    append<WG>(L, lv, fresh, w);
+    uint64_t bal = __ballot(dag != 0ull);
+    bool carry = false;
+    while (bal) {
+        const int j = __builtin_ctzll(bal);
+        bal &= bal - 1ull;
+        const uint32_t wj = __shfl(w, j, 64);
+        const uint64_t dj = shfl64(dag, j);
+        if ((dj >> lane) & 1ull) {
+            unsigned long long* p = (unsigned long long*)&sig[(size_t)wj * 64 + lane];
+            if (safe) {
+                __hip_atomic_fetch_add(p, (unsigned long long)sv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                const unsigned long long old = atomicAdd(p, (unsigned long long)sv);
+                carry |= old + sv < old;
+            }
+        }
+    }
+    if (!safe) {
+        const uint64_t cm = __ballot(carry);
+        if (lane == 0 && cm) atomicOr((unsigned long long*)&L.ovf, (unsigned long long)cm);
+    }
+}
+
+// finishes entry (v, f) of level d with the summed successor psi in `acc`
+__device__ __forceinline__ void finish_entry(const MsbArgs& a, uint64_t* sig, uint32_t v, uint64_t f, double acc,
+                                             uint32_t my_src, uint32_t deg, uint32_t& reached, uint64_t& examined,
+                                             uint32_t& entries, uint64_t& visits) {
+    const unsigned lane = lane_id();
+    double c = 0.0;
+    if ((f >> lane) & 1ull) {
+        uint64_t* cell = &sig[(size_t)v * 64 + lane];
+        const double sigma = (double)*cell;
+        const double delta = sigma * acc;
+        *cell = d2u((1.0 + delta) / sigma);
+        if (my_src != v) c = delta;
+    }
+    c = wave_sum(c);
+    if (lane == 0) {
+        if (c != 0.0) unsafeAtomicAdd(&a.bc[v], c);
+        const uint32_t pc = (uint32_t)__builtin_popcountll(f);
+        reached += pc;
+        examined += (uint64_t)pc * deg;
+        entries += 1;
+        visits += deg;
+    }
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
+    __shared__ MsbLds<WG> L;
+    const unsigned tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
+    constexpr unsigned NW = WG / 64;
+    const size_t n = (size_t)a.n;
+    uint64_t* seen = a.seen + (size_t)blockIdx.x * n;
+    uint64_t* nxt = a.nxt + (size_t)blockIdx.x * n;
+    uint64_t* sig = a.sig + (size_t)blockIdx.x * n * 64;
+    double* hacc = a.hacc + (size_t)blockIdx.x * a.hub_rows * 64;
+    uint32_t* lv = a.lst_v + (size_t)blockIdx.x * a.cap;
+    uint64_t* lm = a.lst_m + (size_t)blockIdx.x * a.cap;
+    uint32_t* lvl = a.lvl + (size_t)blockIdx.x * (a.max_levels + 2);
+    const uint32_t total = *a.plan_count;
+    const uint32_t nbatch = (total + 63) / 64;
+    // per-thread work counters, reduced once at the end
+    uint32_t reached = 0, dagc = 0, entries = 0;
+    uint64_t examined = 0, visits = 0;
+    uint32_t n_done = 0, levels_max = 0;
+
+    for (;;) {
+        if (tid == 0) L.batch = atomicAdd(&a.stats->work_head, 1u);
+        __syncthreads();
+        const uint32_t b = L.batch;
+        __syncthreads();
+        if (b >= nbatch) break;
+        const uint32_t base = b * 64;
+        const uint32_t nl = min(64u, total - base);
+        const uint64_t lanes = nl == 64 ? ~0ull : ((1ull << nl) - 1ull);
+        const uint32_t my_src = lane < nl ? a.plan[base + lane] : 0xffffffffu;
+        if (tid == 0) {
+            L.tail = 0;
+            L.ovf = 0;
+            L.maxsig = 1;
+            L.nhub = 0;
+        }
+        __syncthreads();
+        if (wave == 0) {   // level 0: the sources themselves
+            bool fresh = false;
+            if (lane < nl) {
+                fresh = atomicOr((unsigned long long*)&nxt[my_src], (unsigned long long)(1ull << lane)) == 0ull;
+                sig[(size_t)my_src * 64 + lane] = 1ull;
+            }
+            append<WG>(L, lv, fresh, my_src);
+        }
+        // ---------------- forward sweep ----------------
+        uint32_t lo = 0;
+        uint32_t d = 0;
+        bool stopped = false;     // every thread takes the same decision from the same values
+        uint64_t max_prev = 1;    // largest count on level d-1
+        for (;;) {
+            level_barrier();
+            const uint32_t hi = L.tail;
+            if (tid == 0) L.sdeg = 0;
+            __syncthreads();
+            // fix the masks of the level-d entries and fold them into seen
+            uint32_t sdeg = 0;
+            for (uint32_t i = lo + tid; i < hi; i += WG) {
+                const uint32_t w = lv[i];
+                const uint64_t m = nxt[w];
+                lm[i] = m;
+                seen[w] |= m;
+                nxt[w] = 0ull;
+                sdeg += a.row_ptr[w + 1] - a.row_ptr[w];
+            }
+            sdeg = wave_sum_u32(sdeg);
+            if (lane == 0 && sdeg) atomicAdd(&L.sdeg, sdeg);
+            if (tid == 0) {
+                lvl[d] = lo;
+                lvl[d + 1] = hi;
+            }
+            level_barrier();
+            if (hi == lo) break;   // level d is empty: the sweep is over (levels 0..d-1)
+            const uint64_t room = (uint64_t)a.cap - hi;
+            if (d + 2 > a.max_levels || room < min<uint64_t>(n, L.sdeg)) {
+                stopped = true;
+                d += 1;
+                break;
+            }
+            const uint64_t max_here = L.maxsig;   // largest count seen while expanding level d-1
+            if (d >= 1) max_prev = max_here;
+            const bool safe = d == 0 || (double)max_prev * a.in2 < kSafeSigma;
+            __syncthreads();
+            if (tid == 0) L.maxsig = 0;
+            __syncthreads();
+            for (uint32_t c0 = lo; c0 < hi; c0 += WG) {
+                const uint32_t i = c0 + tid;
+                uint32_t v = 0, beg = 0, deg = 0;
+                uint64_t f = 0;
+                if (i < hi) {
+                    v = lv[i];
+                    f = lm[i];
+                    beg = a.row_ptr[v];
+                    deg = a.row_ptr[v + 1] - beg;
+                }
+                uint32_t units;
+                const uint32_t off = block_excl_scan<WG>((deg + 63) / 64, units, L.wsum);
+                L.off[tid] = off;
+                L.ev[tid] = v;
+                L.em[tid] = f;
+                L.eb[tid] = beg;
+                L.ed[tid] = deg;
+                __syncthreads();
+                for (uint32_t u = wave; u < units; u += NW) {
+                    const uint32_t j = find_owner<WG>(L.off, u);
+                    const uint32_t e0 = L.eb[j] + (u - L.off[j]) * 64;
+                    const uint32_t e1 = min(L.eb[j] + L.ed[j], e0 + 64);
+                    fwd_unit<WG>(a, L, seen, nxt, sig, lv, L.ev[j], L.em[j], e0, e1, safe);
+                }
+                __syncthreads();
+            }
+            lo = hi;
+            ++d;
+        }
+        const uint32_t nlev = d;            // levels 0..nlev-1 hold entries
+        const uint32_t n_entries = L.tail;
+        const uint64_t ovf = stopped ? lanes : (L.ovf & lanes);
+        // ---------------- backward sweep ----------------
+        if (!stopped) {
+            if (tid == 0) lvl[nlev + 1] = lvl[nlev];
+            level_barrier();
+            for (int dd = (int)nlev - 1; dd >= 0; --dd) {
+                const uint32_t lo_d = lvl[dd], hi_d = lvl[dd + 1];
+                const uint32_t lo_n = lvl[dd + 1], hi_n = lvl[dd + 2];
+                for (uint32_t i = lo_n + tid; i < hi_n; i += WG) nxt[lv[i]] = lm[i] & ~ovf;
+                level_barrier();
+                for (uint32_t c0 = lo_d; c0 < hi_d; c0 += WG) {
+                    const uint32_t i = c0 + tid;
+                    uint32_t v = 0, beg = 0, deg = 0, np = 0;
+                    uint64_t f = 0;
+                    if (i < hi_d) {
+                        v = lv[i];
+                        f = lm[i] & ~ovf;
+                        beg = a.row_ptr[v];
+                        deg = a.row_ptr[v + 1] - beg;
+                        if (f) np = deg > 64 ? (deg + 63) / 64 : 1u;
+                    }
+                    int32_t row = -1;
+                    if (np > 1) {
+                        row = (int32_t)atomicAdd(&L.nhub, 1u);
+                        L.hub_ent[row] = tid;
+                        for (int q = 0; q < 64; ++q) hacc[(size_t)row * 64 + q] = 0.0;
+                    }
+                    uint32_t units;
+                    const uint32_t off = block_excl_scan<WG>(np, units, L.wsum);
+                    L.off[tid] = off;
+                    L.ev[tid] = v;
+                    L.em[tid] = f;
+                    L.eb[tid] = beg;
+                    L.ed[tid] = deg;
+                    L.eh[tid] = row;
+                    level_barrier();
+                    for (uint32_t u = wave; u < units; u += NW) {
+                        const uint32_t j = find_owner<WG>(L.off, u);
+                        const uint32_t vj = L.ev[j];
+                        const uint64_t fj = L.em[j];
+                        const uint32_t dj = L.ed[j];
+                        const uint32_t e0 = L.eb[j] + (u - L.off[j]) * 64;
+                        const uint32_t e1 = min(L.eb[j] + dj, e0 + 64);
+                        const uint32_t e = e0 + lane;
+                        uint32_t w = 0;
+                        uint64_t sm = 0;
+                        if (e < e1) {
+                            w = a.col[e];
+                            sm = fj & nxt[w];
+                        }
+                        dagc += (uint32_t)__builtin_popcountll(sm);
+                        uint64_t bal = __ballot(sm != 0ull);
+                        double acc = 0.0;
+                        while (bal) {
+                            const int q = __builtin_ctzll(bal);
+                            bal &= bal - 1ull;
+                            const uint32_t wq = __shfl(w, q, 64);
+                            const uint64_t mq = shfl64(sm, q);
+                            if ((mq >> lane) & 1ull) acc += u2d(sig[(size_t)wq * 64 + lane]);
+                        }
+                        const int32_t hr = L.eh[j];
+                        if (hr < 0) {
+                            finish_entry(a, sig, vj, fj, acc, my_src, dj, reached, examined, entries, visits);
+                        } else if (((fj >> lane) & 1ull) && acc != 0.0) {
+                            unsafeAtomicAdd(&hacc[(size_t)hr * 64 + lane], acc);
+                        }
+                    }
+                    level_barrier();
+                    const uint32_t nh = L.nhub;
+                    for (uint32_t h = wave; h < nh; h += NW) {
+                        const uint32_t j = L.hub_ent[h];
+                        finish_entry(a, sig, L.ev[j], L.em[j], hacc[(size_t)h * 64 + lane], my_src, L.ed[j], reached,
+                                     examined, entries, visits);
+                    }
+                    __syncthreads();
+                    if (tid == 0) L.nhub = 0;
+                    __syncthreads();
+                }
+                for (uint32_t i = lo_n + tid; i < hi_n; i += WG) nxt[lv[i]] = 0ull;
+                level_barrier();
+            }
+        }
+        // ---------------- reset the touched state ----------------
+        for (uint32_t i = wave; i < n_entries; i += NW) {
+            const uint32_t v = lv[i];
+            uint64_t m = lm[i];
+            if (stopped && i >= lvl[nlev]) m = ~0ull;   // defensive: entries never finalised
+            if ((m >> lane) & 1ull) sig[(size_t)v * 64 + lane] = 0ull;
+            if (lane == 0) {
+                seen[v] = 0ull;
+                nxt[v] = 0ull;
+            }
+        }
+        // sources this kernel did not finish go to the per-source kernel
+        if (tid == 0) {
+            if (ovf) {
+                const uint32_t cnt = (uint32_t)__builtin_popcountll(ovf);
+                uint32_t pos = atomicAdd(a.retry_count, cnt);
+                uint64_t m = ovf;
+                while (m) {
+                    const int s = __builtin_ctzll(m);
+                    m &= m - 1ull;
+                    a.retry[pos++] = a.plan[base + s];
+                }
+            }
+            n_done += (uint32_t)__builtin_popcountll(lanes & ~ovf);
+            if (!stopped) levels_max = max(levels_max, nlev);
+        }
+        level_barrier();
+    }
+    // counters of everything this workgroup finished
+    const uint32_t r_w = wave_sum_u32(reached), g_w = wave_sum_u32(dagc), n_w = wave_sum_u32(entries);
+    uint64_t e_w = examined, v_w = visits;
+#pragma unroll
+    for (int dsh = 32; dsh > 0; dsh >>= 1) {
+        e_w += (uint64_t)__shfl_xor((long long)e_w, dsh, 64);
+        v_w += (uint64_t)__shfl_xor((long long)v_w, dsh, 64);
+    }
+    if (lane == 0) {
+        if (r_w) atomicAdd((unsigned long long*)&a.stats->reached, (unsigned long long)r_w);
+        if (e_w) atomicAdd((unsigned long long*)&a.stats->examined, (unsigned long long)e_w);
+        if (g_w) atomicAdd((unsigned long long*)&a.stats->dag_edges, (unsigned long long)g_w);
+        if (n_w) atomicAdd((unsigned long long*)&a.stats->entries, (unsigned long long)n_w);
+        if (v_w) atomicAdd((unsigned long long*)&a.stats->edge_visits, (unsigned long long)v_w);
+    }
+    if (tid == 0) {
+        if (n_done) atomicAdd(&a.stats->n_done, n_done);
+        if (levels_max) atomicMax(&a.stats->levels_max, levels_max);
+    }
+}
+
+// ---- source plan: valid sources with out-edges, grouped by out-degree (largest first) ----
+constexpr int kPlanBuckets = 33;   // bucket q = count of leading zeros of the out-degree; 32 = no out-edges
+
+__global__ void k_plan_hist(const uint32_t* row_ptr, const uint32_t* srcs, uint32_t k, uint32_t n, uint32_t* hist,
+                            CallStats* stats) {
+    __shared__ uint32_t h[kPlanBuckets];
+    if (threadIdx.x < kPlanBuckets) h[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        const uint32_t s = srcs ? srcs[i] : i;
+        if (s >= n) {
+            ++bad;
+            continue;
+        }
+        const uint32_t deg = row_ptr[s + 1] - row_ptr[s];
+        atomicAdd(&h[deg ? __clz(deg) : 32], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kPlanBuckets && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+    if (bad) atomicAdd(&stats->bad_source, bad);
+}
+
+__global__ void k_plan_scan(const uint32_t* hist, uint32_t* cursor, uint32_t* plan_count, CallStats* stats) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int q = 0; q < kPlanBuckets; ++q) {
+        cursor[q] = run;
+        run += hist[q];
+    }
+    const uint32_t idle = hist[kPlanBuckets - 1];
+    plan_count[0] = run - idle;
+    // sources without out-edges: finished here (they reach only themselves)
+    stats->n_done += idle;
+    stats->reached += idle;
+    if (idle && stats->levels_max < 1) stats->levels_max = 1;
+}
+
+__global__ void k_plan_scatter(const uint32_t* row_ptr, const uint32_t* srcs, uint32_t k, uint32_t n,
+                               uint32_t* cursor, uint32_t* plan) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        const uint32_t s = srcs ? srcs[i] : i;
+        if (s >= n) continue;
+        const uint32_t deg = row_ptr[s + 1] - row_ptr[s];
+        if (!deg) continue;
+        plan[atomicAdd(&cursor[__clz(deg)], 1u)] = s;
+    }
+}
+
+__global__ void k_zero_u32(uint32_t* p, uint32_t count) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+__global__ void k_zero_u64(uint64_t* p, size_t count) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+const void* msb_fn(int wg) {
+    switch (wg) {
+        case 256: return (const void*)k_msb<256>;
+        case 512: return (const void*)k_msb<512>;
+        default: return (const void*)k_msb<1024>;
+    }
+}
+
+}  // namespace
+
+int msb_norm_wg(int wg) { return wg <= 256 ? 256 : (wg <= 512 ? 512 : 1024); }
+
+int msb_occupancy(int wg) {
+    int per_cu = 0;
+    BC_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, msb_fn(wg), wg, 0));
+    return per_cu;
+}
+
+// Device state of the batched path for one graph size, reused between calls.
+struct MsbPool {
+    int slots = 0;
+    uint32_t n = 0, cap = 0, max_levels = 0, hub_rows = 0;
+    uint64_t *seen = nullptr, *nxt = nullptr, *sig = nullptr, *lst_m = nullptr;
+    double* hacc = nullptr;
+    uint32_t *lst_v = nullptr, *lvl = nullptr;
+    uint32_t* plan = nullptr;       // [plan_cap]
+    uint32_t* retry = nullptr;      // [plan_cap]
+    uint32_t plan_cap = 0;
+    uint32_t* small = nullptr;      // hist[33] cursor[33] plan_count retry_count
+};
+
+size_t msb_slot_bytes(uint32_t n, uint32_t cap, uint32_t max_levels, uint32_t hub_rows) {
+    return (size_t)n * (8 + 8 + 512) + (size_t)cap * 12 + 4 * ((size_t)max_levels + 2) + (size_t)hub_rows * 512;
+}
+
+void msb_pool_free(MsbPool& p) {
+    for (void* q : {(void*)p.seen, (void*)p.nxt, (void*)p.sig, (void*)p.lst_m, (void*)p.hacc, (void*)p.lst_v,
+                    (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small})
+        if (q) (void)hipFree(q);
+    p = MsbPool{};
+}
+
+MsbPool* msb_pool_new() { return new MsbPool(); }
+void msb_pool_delete(MsbPool* p) {
+    if (p) {
+        msb_pool_free(*p);
+        delete p;
+    }
+}
+
+static void msb_pool_ensure(MsbPool& p, uint32_t n, int slots, uint32_t cap, uint32_t max_levels, uint32_t hub_rows,
+                            uint32_t plan_cap, hipStream_t st) {
+    if (p.seen && p.n == n && p.slots >= slots && p.cap >= cap && p.max_levels >= max_levels &&
+        p.hub_rows >= hub_rows && p.plan_cap >= plan_cap)
+        return;
+    BC_HIP_TRY(hipStreamSynchronize(st));
+    msb_pool_free(p);
+    p.n = n;
+    p.slots = slots;
+    p.cap = cap;
+    p.max_levels = max_levels;
+    p.hub_rows = hub_rows;
+    p.plan_cap = std::max<uint32_t>(plan_cap, 1);
+    BC_HIP_TRY(hipMalloc((void**)&p.seen, (size_t)slots * n * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.nxt, (size_t)slots * n * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.sig, (size_t)slots * n * 512));
+    BC_HIP_TRY(hipMalloc((void**)&p.hacc, (size_t)slots * hub_rows * 512));
+    BC_HIP_TRY(hipMalloc((void**)&p.lst_v, (size_t)slots * cap * 4));
+    BC_HIP_TRY(hipMalloc((void**)&p.lst_m, (size_t)slots * cap * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.lvl, (size_t)slots * (max_levels + 2) * 4));
+    BC_HIP_TRY(hipMalloc((void**)&p.plan, (size_t)p.plan_cap * 4));
+    BC_HIP_TRY(hipMalloc((void**)&p.retry, (size_t)p.plan_cap * 4));
+    BC_HIP_TRY(hipMalloc((void**)&p.small, 128 * 4));
+    const size_t words = (size_t)slots * n;
+    const unsigned g1 = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.seen, words);
+    hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.nxt, words);
+    const unsigned g2 = (unsigned)std::min<size_t>((words * 64 + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero_u64, dim3(g2), dim3(256), 0, st, p.sig, words * 64);
+    BC_HIP_TRY(hipGetLastError());
+}
+
+// Enqueues the batched path: source plan, batched sweeps, then the per-source kernel on the
+// sources handed back.  `retry_launch` enqueues that per-source launch over (list, count).
+void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
+                     int wg, int slots_cap, hipStream_t st,
+                     void (*retry_launch)(void*, const uint32_t*, const uint32_t*, uint32_t, hipStream_t),
+                     void* retry_ctx) {
+    const DevInfo& di = dev_info(g.device);
+    wg = msb_norm_wg(wg);
+    const uint32_t n = (uint32_t)g.n;
+    const uint32_t active_max = sources ? k : (uint32_t)(g.n - g.zero_out_degree);
+    const uint32_t batches = (active_max + 63) / 64;
+    int per_cu = msb_occupancy(wg);
+    BC_REQUIRE(per_cu >= 1, BC_E_HIP, "batched kernel does not fit on a compute unit");
+    int slots = std::min<long>((long)per_cu * di.cus, std::max<uint32_t>(batches, 1));
+    if (slots_cap > 0) slots = std::min(slots, slots_cap);
+    const uint32_t cap = (uint32_t)std::min<uint64_t>((uint64_t)n * 8 + 64, 0xffffffffull);
+    const uint32_t max_levels = 1024;
+    // bound the pool by free device memory (keep half of it for everything else)
+    size_t free_b = 0, total_b = 0;
+    BC_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const size_t per_slot = msb_slot_bytes(n, cap, max_levels, (uint32_t)wg);
+    const size_t have = (size_t)p.slots >= (size_t)slots && p.n == n ? (size_t)p.slots * per_slot : 0;
+    const size_t budget = (free_b + have) / 2;
+    slots = (int)std::max<size_t>(1, std::min<size_t>(slots, budget / std::max<size_t>(per_slot, 1)));
+    msb_pool_ensure(p, n, slots, cap, max_levels, (uint32_t)wg, std::max<uint32_t>(k, n), st);
+
+    uint32_t* hist = p.small;
+    uint32_t* cursor = p.small + 40;
+    uint32_t* plan_count = p.small + 80;
+    uint32_t* retry_count = p.small + 81;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, st, p.small, 128u);
+    const uint32_t items = sources ? k : n;
+    const unsigned gp = std::max(1u, std::min<unsigned>((items + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_plan_hist, dim3(gp), dim3(256), 0, st, g.row_ptr, sources, items, n, hist, stats);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, st, hist, cursor, plan_count, stats);
+    hipLaunchKernelGGL(k_plan_scatter, dim3(gp), dim3(256), 0, st, g.row_ptr, sources, items, n, cursor, p.plan);
+    BC_HIP_TRY(hipGetLastError());
+
+    MsbArgs a{};
+    a.row_ptr = g.row_ptr;
+    a.col = g.col;
+    a.bc = bc;
+    a.plan = p.plan;
+    a.plan_count = plan_count;
+    a.retry = p.retry;
+    a.retry_count = retry_count;
+    a.stats = stats;
+    a.seen = p.seen;
+    a.nxt = p.nxt;
+    a.sig = p.sig;
+    a.hacc = p.hacc;
+    a.lst_v = p.lst_v;
+    a.lst_m = p.lst_m;
+    a.lvl = p.lvl;
+    a.n = g.n;
+    a.cap = p.cap;
+    a.max_levels = p.max_levels;
+    a.hub_rows = p.hub_rows;
+    a.in2 = (double)g.max_in_degree * (double)g.max_in_degree;
+    switch (wg) {
+        case 256: hipLaunchKernelGGL(k_msb<256>, dim3(slots), dim3(256), 0, st, a); break;
+        case 512: hipLaunchKernelGGL(k_msb<512>, dim3(slots), dim3(512), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_msb<1024>, dim3(slots), dim3(1024), 0, st, a); break;
+    }
+    BC_HIP_TRY(hipGetLastError());
+    retry_launch(retry_ctx, p.retry, retry_count, std::max<uint32_t>(k, n), st);
+}
+
+}  // namespace bcmi

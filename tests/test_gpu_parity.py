@@ -101,37 +101,81 @@ def test_sssp_bit_exact(bc, scale, ef, seed):
 # ---------------------------------------------------------------------------------------
 # exact BC, both state homes, every expansion strategy
 # ---------------------------------------------------------------------------------------
-def test_exact_rmat_scale10_both_paths(bc):
+def test_exact_rmat_scale10_every_path(bc):
     n, u, v = gg.rmat(10, 8, 10)
     g = bc.bc_build_csr(n, u, v)
     want, ovf, st = oracle.bc(oracle.Graph(n, u, v))
-    for lds in (0, -1):
-        say("exact s10 lds_max_n", lds)
-        got, info = bc.bc_exact(g, tuning=bc.tuning(lds_max_n=lds) if lds else None, info=True)
-        assert info["path"] == (1 if lds == 0 else 0)
+    for path in PATHS:
+        say("exact s10", path)
+        got, info = bc.bc_exact(g, tuning=force(bc, path), info=True)
+        assert info["path"] == PATH_CODE[path]
         assert info["n_sources"] == n and info["n_sigma_fp64_fallback"] == 0
         assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
-        rel_close(np_of(got), want, what=f"bc lds={lds}")
+        rel_close(np_of(got), want, what=f"bc {path}")
     g.free()
+
+
+PATHS = {
+    "lds": dict(lds_max_n=4096, batched=-1),
+    "global": dict(lds_max_n=-1, batched=-1),
+    "batched": dict(lds_max_n=-1, batched=1),
+}
+PATH_CODE = {"lds": 1, "global": 0, "batched": 2}
+
+
+def force(bc, path, **kw):
+    return bc.tuning(**PATHS[path], **kw)
+
+
+_oracle_cache = {}
+
+
+def oracle_exact(key, n, u, v):
+    if key not in _oracle_cache:
+        _oracle_cache[key] = oracle.bc(oracle.Graph(n, u, v))
+    return _oracle_cache[key]
 
 
 @pytest.mark.parametrize("wg", [64, 256, 1024])
 @pytest.mark.parametrize("hub", [1, 16, -1])
-@pytest.mark.parametrize("lds", [4096, -1])
-def test_strategies_agree(bc, wg, hub, lds):
+@pytest.mark.parametrize("path", ["lds", "global"])
+def test_strategies_agree(bc, wg, hub, path):
     n, u, v = gg.rmat(11, 16, 4)
-    key = (n, len(u))
-    if not hasattr(test_strategies_agree, "cache"):
-        test_strategies_agree.cache = {}
-    cache = test_strategies_agree.cache
-    if key not in cache:
-        cache[key] = oracle.bc(oracle.Graph(n, u, v))[0]
-    want = cache[key]
-    say("strategy wg", wg, "hub", hub, "lds", lds)
+    want = oracle_exact("rmat11", n, u, v)[0]
+    say("strategy", path, "wg", wg, "hub", hub)
     g = bc.bc_build_csr(n, u, v)
-    got, info = bc.bc_exact(g, tuning=bc.tuning(wg_size=wg, hub_threshold=hub, lds_max_n=lds), info=True)
-    assert info["path"] == (1 if lds > 0 else 0)
-    rel_close(np_of(got), want, what=f"wg={wg} hub={hub} lds={lds}")
+    got, info = bc.bc_exact(g, tuning=force(bc, path, wg_size=wg, hub_threshold=hub), info=True)
+    assert info["path"] == PATH_CODE[path]
+    rel_close(np_of(got), want, what=f"wg={wg} hub={hub} path={path}")
+    g.free()
+
+
+@pytest.mark.parametrize("bwg", [256, 512, 1024])
+@pytest.mark.parametrize("case", ["rmat11", "rmat9_ef4"])
+def test_batched_exact(bc, bwg, case):
+    sc, ef, seed = (11, 16, 4) if case == "rmat11" else (9, 4, 2)
+    n, u, v = gg.rmat(sc, ef, seed)
+    want, ovf, st = oracle_exact(case, n, u, v)
+    say("batched", case, bwg)
+    g = bc.bc_build_csr(n, u, v)
+    got, info = bc.bc_exact(g, tuning=force(bc, "batched", batch_wg_size=bwg), info=True)
+    assert info["path"] == 2 and info["n_sources"] == n
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    assert info["levels_max"] == int(st[:, 3].max())
+    rel_close(np_of(got), want, what=f"batched wg={bwg}")
+    g.free()
+
+
+def test_batched_sampled_multiset(bc):
+    n, u, v = gg.rmat(12, 8, 9)
+    g = bc.bc_build_csr(n, u, v)
+    S = gg.uniform_sources(n, 300, 1)
+    S = np.concatenate([S, S[:50], np.zeros(3, np.uint32)])     # repeats, and vertex 0 thrice
+    got, info = bc.bc_sampled(g, S, tuning=force(bc, "batched"), info=True)
+    want, _, st = oracle.bc(oracle.Graph(n, u, v), S)
+    assert info["n_sources"] == len(S)
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    rel_close(np_of(got), want)
     g.free()
 
 
@@ -153,10 +197,11 @@ def test_overflow_diamond_chain(bc, k):
     rel_close(np_of(r["sigma_f64"]), w["sigma_f"], 1e-12, "sigma_f64")
     rel_close(np_of(r["delta"]), w["delta"], what="delta")
     want, ovf, _ = oracle.bc(o)
-    for lds in (0, -1):
-        got, info = bc.bc_exact(g, tuning=bc.tuning(lds_max_n=lds) if lds else None, info=True)
+    for path in PATHS:
+        got, info = bc.bc_exact(g, tuning=force(bc, path), info=True)
+        assert info["path"] == PATH_CODE[path]
         assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
-        rel_close(np_of(got), want, what="bc")
+        rel_close(np_of(got), want, what=f"bc {path}")
     g.free()
 
 
@@ -166,11 +211,11 @@ def test_overflow_grid_dag(bc):
     o = oracle.Graph(n, u, v)
     want, ovf, _ = oracle.bc(o)
     assert ovf.sum() >= 1
-    for lds in (0, -1):
-        say("grid dag 35 lds", lds)
-        got, info = bc.bc_exact(g, tuning=bc.tuning(lds_max_n=lds) if lds else None, info=True)
+    for path in PATHS:
+        say("grid dag 35", path)
+        got, info = bc.bc_exact(g, tuning=force(bc, path), info=True)
         assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
-        rel_close(np_of(got), want, what="bc")
+        rel_close(np_of(got), want, what=f"bc {path}")
     # the overflowing source set itself, one source at a time
     for s in [0, 1, 35, 36, 70]:
         assert bc.bc_sssp(g, s)["overflow"] == bool(oracle.brandes_source(o, s)["overflow"])
@@ -182,10 +227,11 @@ def test_high_diameter_lattice(bc):
     g = bc.bc_build_csr(n, u, v)
     o = oracle.Graph(n, u, v)
     want, ovf, st = oracle.bc(o)
-    for lds in (0, -1):
-        say("lattice 64x64 lds", lds)
-        got, info = bc.bc_exact(g, tuning=bc.tuning(lds_max_n=lds) if lds else None, info=True)
+    for path in PATHS:     # the batched path runs out of level-list room here and hands back
+        say("lattice 64x64", path)
+        got, info = bc.bc_exact(g, tuning=force(bc, path), info=True)
         assert info["levels_max"] == int(st[:, 3].max())
+        assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
         assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
         rel_close(np_of(got), want, what="bc")
     g.free()
@@ -205,8 +251,8 @@ def test_edge_cases(bc):
     g.free()
     n, u, v = gg.directed_path(700)     # deep, one vertex per level
     g = bc.bc_build_csr(n, u, v)
-    for lds in (0, -1):
-        got = np_of(bc.bc_exact(g, tuning=bc.tuning(lds_max_n=lds) if lds else None))
+    for path in PATHS:
+        got = np_of(bc.bc_exact(g, tuning=force(bc, path)))
         assert got.tolist() == [float(i * (n - 1 - i)) for i in range(n)]
     out = torch.full((n,), 7.0, dtype=torch.float64, device="cuda")
     bc.bc_sampled(g, np.zeros(0, np.uint32), out=out)
@@ -245,14 +291,16 @@ def test_rmat_scale16_sampled_subset(bc):
     n, u, v = gg.rmat(16, 16, 16)
     g = bc.bc_build_csr(n, u, v)
     S = gg.uniform_sources(n, 256, 1616)
-    say("rmat16 sampled 256")
-    got, info = bc.bc_sampled(g, S, info=True)
     want, ovf, st = oracle.bc(oracle.Graph(n, u, v), S)
-    assert info["n_sigma_fp64_fallback"] == int(ovf.sum()) == 0
-    # exact work counters: reached vertices, examined edges, DAG edges, deepest level
-    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
-    assert info["levels_max"] == int(st[:, 3].max())
-    rel_close(np_of(got), want)
+    for path in ["global", "batched"]:
+        say("rmat16 sampled 256", path)
+        got, info = bc.bc_sampled(g, S, tuning=force(bc, path), info=True)
+        assert info["path"] == PATH_CODE[path]
+        assert info["n_sigma_fp64_fallback"] == int(ovf.sum()) == 0
+        # exact work counters: reached vertices, examined edges, DAG edges, deepest level
+        assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+        assert info["levels_max"] == int(st[:, 3].max())
+        rel_close(np_of(got), want)
     g.free()
 
 
