@@ -133,11 +133,15 @@ def bench_single(args, torch, bcmi, gg):
     if args.tune:
         tune = bcmi.bc_tune(g)
     tun = bcmi.tuning(**{k: v for k, v in (tune or {}).items()}) if tune else None
-    if args.strategy != "auto":
-        force = {"batched": dict(batched=1), "per-source": dict(batched=-1)}[args.strategy]
+    if args.strategy != "auto" or args.knob:
         base = dict(tune or {})
-        base.update(force)
+        if args.strategy != "auto":
+            base.update({"batched": dict(batched=1), "per-source": dict(batched=-1)}[args.strategy])
+        for kv in args.knob:
+            key, val = kv.split("=")
+            base[key] = int(val)
         tun = bcmi.tuning(**base)
+        tune = base
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     d_src = torch.from_numpy(sources.view(np.int32)).cuda()
 
@@ -237,8 +241,11 @@ def main():
     ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat20", "lattice", "batch"])
     ap.add_argument("--tune", action="store_true", help="autotune launch knobs first (untimed)")
     ap.add_argument("--strategy", default="auto", choices=["auto", "batched", "per-source"])
+    ap.add_argument("--knob", action="append", default=[], help="launch knob override, e.g. batch_wg_size=512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 2 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the method shards over sources with one final sum of the "
@@ -251,6 +258,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     bcmi.lib()
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.workload == "batch":
         res = bench_batch(args, torch, bcmi, gg)
     else:

@@ -66,9 +66,6 @@ __device__ __forceinline__ unsigned lane_id() {
 }
 __device__ __forceinline__ double u2d(uint64_t x) { return __longlong_as_double((long long)x); }
 __device__ __forceinline__ uint64_t d2u(double x) { return (uint64_t)__double_as_longlong(x); }
-__device__ __forceinline__ uint64_t shfl64(uint64_t x, int j) {
-    return (uint64_t)__shfl((long long)x, j, 64);
-}
 __device__ __forceinline__ uint64_t wave_max64(uint64_t x) {
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {
@@ -112,6 +109,8 @@ struct MsbLds {
     uint32_t ed[WG];        // out-degree
     int32_t eh[WG];         // accumulator row of a split entry, -1 otherwise
     uint32_t hub_ent[WG];   // accumulator row -> chunk entry
+    uint32_t sw[WG / 64][64];   // per wavefront: compacted (successor, source mask) pairs of a unit
+    uint64_t sm[WG / 64][64];
     uint32_t nhub;
     uint32_t tail;          // level-list append position
     uint32_t batch;
@@ -183,13 +182,20 @@ __device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, uint64
         if (dag) fresh = atomicOr((unsigned long long*)&nxt[w], (unsigned long long)dag) == 0ull;
     }
     append<WG>(L, lv, fresh, w);
-    uint64_t bal = __ballot(dag != 0ull);
+    // phase B, lane per source: the unit's DAG edges, compacted in LDS, one row update each
+    const uint64_t bal = __ballot(dag != 0ull);
+    const uint32_t cnt = (uint32_t)__builtin_popcountll(bal);
+    const unsigned wv = threadIdx.x / 64;
+    if (dag) {
+        const uint32_t pos = (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
+        L.sw[wv][pos] = w;
+        L.sm[wv][pos] = dag;
+    }
+    __builtin_amdgcn_wave_barrier();
     bool carry = false;
-    while (bal) {
-        const int j = __builtin_ctzll(bal);
-        bal &= bal - 1ull;
-        const uint32_t wj = __shfl(w, j, 64);
-        const uint64_t dj = shfl64(dag, j);
+    for (uint32_t k = 0; k < cnt; ++k) {
+        const uint32_t wj = L.sw[wv][k];
+        const uint64_t dj = L.sm[wv][k];
         if ((dj >> lane) & 1ull) {
             unsigned long long* p = (unsigned long long*)&sig[(size_t)wj * 64 + lane];
             if (safe) {
@@ -200,6 +206,7 @@ __device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, uint64
             }
         }
     }
+    __builtin_amdgcn_wave_barrier();
     if (!safe) {
         const uint64_t cm = __ballot(carry);
         if (lane == 0 && cm) atomicOr((unsigned long long*)&L.ovf, (unsigned long long)cm);
@@ -397,15 +404,30 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                             sm = fj & nxt[w];
                         }
                         dagc += (uint32_t)__builtin_popcountll(sm);
-                        uint64_t bal = __ballot(sm != 0ull);
-                        double acc = 0.0;
-                        while (bal) {
-                            const int q = __builtin_ctzll(bal);
-                            bal &= bal - 1ull;
-                            const uint32_t wq = __shfl(w, q, 64);
-                            const uint64_t mq = shfl64(sm, q);
-                            if ((mq >> lane) & 1ull) acc += u2d(sig[(size_t)wq * 64 + lane]);
+                        // lane per source: sum psi over the unit's successors, loads issued
+                        // eight at a time from the compacted list
+                        const uint64_t bal = __ballot(sm != 0ull);
+                        const uint32_t cnt = (uint32_t)__builtin_popcountll(bal);
+                        if (sm) {
+                            const uint32_t pos = (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
+                            L.sw[wave][pos] = w;
+                            L.sm[wave][pos] = sm;
                         }
+                        __builtin_amdgcn_wave_barrier();
+                        double acc = 0.0;
+                        for (uint32_t k = 0; k < cnt; k += 8) {
+                            double x[8];
+#pragma unroll
+                            for (int t = 0; t < 8; ++t) {
+                                const bool okt = k + t < cnt;
+                                const uint32_t wt = okt ? L.sw[wave][k + t] : 0u;
+                                const uint64_t mt = okt ? L.sm[wave][k + t] : 0ull;
+                                x[t] = ((mt >> lane) & 1ull) ? u2d(sig[(size_t)wt * 64 + lane]) : 0.0;
+                            }
+#pragma unroll
+                            for (int t = 0; t < 8; ++t) acc += x[t];
+                        }
+                        __builtin_amdgcn_wave_barrier();
                         const int32_t hr = L.eh[j];
                         if (hr < 0) {
                             finish_entry(a, sig, vj, fj, acc, my_src, dj, reached, examined, entries, visits);
