@@ -191,44 +191,142 @@ def bench_single(args, torch, bcmi, gg):
             "kernel_ms_all": [i["kernel_ms"] for i in infos],
         },
     }
+    if args.plain_baseline:
+        per = one_source_per_launch_ms(bcmi, torch, g, sources, 256)
+        res["extra"]["one_launch_per_source_ms_estimated"] = per * k
+        res["extra"]["speedup_vs_launch_per_source"] = per * k / ms_per_step
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(n, u, v, sources, g.m, args.cpu_seconds)
     g.free()
     return res
 
 
+def one_source_per_launch_ms(bcmi, torch, g, sources, reps):
+    """Mean time of the plain path: one launch per source (bc_sampled with k = 1)."""
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    one = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tun = bcmi.tuning(batched=-1)
+    bcmi.bc_sampled(g, one, out=out, tuning=tun)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sources[:reps]:
+        one.fill_(int(s))
+        bcmi.bc_sampled(g, one, out=out, tuning=tun)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / min(reps, len(sources))
+
+
 def bench_batch(args, torch, bcmi, gg):
     rng = np.random.default_rng(4096)
     scales = rng.integers(6, 13, size=4096)
     specs = [(int(s), 8, 4096_000 + i) for i, s in enumerate(scales)]
-    graphs, coo = [], []
+    graphs = []
     t0 = time.perf_counter()
     for sc, ef, seed in specs:
         n, u, v = gg.rmat(sc, ef, seed)
-        coo.append((n, u, v))
         graphs.append(bcmi.bc_build_csr(n, u, v))
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
     outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in graphs]
-    tun = None
     for _ in range(args.warmup):
-        bcmi.bc_batch(graphs, outs, tuning=tun, info=True)
+        bcmi.bc_batch(graphs, outs, info=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
     for _ in range(args.steps):
-        infos.append(bcmi.bc_batch(graphs, outs, tuning=tun, info=True)[1])
+        infos.append(bcmi.bc_batch(graphs, outs, info=True)[1])
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     nominal = sum(g.n * g.m for g in graphs)
+    # the same work as one exact launch per graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, o in zip(graphs, outs):
+        bcmi.bc_exact(g, out=o)
+    torch.cuda.synchronize()
+    per_graph_ms = (time.perf_counter() - t0) * 1e3
+    # one launch per source, timed on a sample and scaled to every source
+    sample_ms = []
+    for g in graphs[:16]:
+        sample_ms.append(one_source_per_launch_ms(bcmi, torch, g, np.arange(g.n), 32))
+    per_source_ms = float(np.mean(sample_ms)) * sum(g.n for g in graphs)
     res = {"metric": "GTEPS (sources x edges / s), nominal, batched exact BC", "value": nominal / (ms / 1e3) / 1e9,
            "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "u64+f64", "data": "synthetic",
            "config": {"workload": "batch4096-rmat6to12-ef8", "graphs": 4096,
                       "sum_n": int(sum(g.n for g in graphs)), "sum_m": int(sum(g.m for g in graphs))},
-           "extra": {"build_csr_ms_total": build_ms, "kernel_ms": infos[-1][0]["kernel_ms"]}}
+           "extra": {"build_csr_ms_total": build_ms, "kernel_ms": infos[-1][0]["kernel_ms"],
+                     "one_exact_launch_per_graph_ms": per_graph_ms,
+                     "one_launch_per_source_ms_estimated": per_source_ms,
+                     "speedup_vs_launch_per_graph": per_graph_ms / ms,
+                     "speedup_vs_launch_per_source": per_source_ms / ms}}
     for g in graphs:
+        g.free()
+    return res
+
+
+def bench_serve(args, torch, bcmi, gg):
+    """Poisson stream of BC requests over a pool of resident R-MAT graphs."""
+    rng = np.random.default_rng(5)
+    pool = []
+    for i in range(64):
+        sc = int(rng.integers(8, args.serve_max_scale + 1))
+        ef = int(rng.integers(4, 17))
+        n, u, v = gg.rmat(sc, ef, 5000 + i)
+        pool.append(bcmi.bc_build_csr(n, u, v))
+    torch.cuda.synchronize()
+    N = args.serve_requests
+    gaps = rng.exponential(1.0 / args.serve_rate, size=N)
+    arrive = np.cumsum(gaps)
+    reqs = []
+    for i in range(N):
+        g = pool[int(rng.integers(0, len(pool)))]
+        if rng.random() < 0.7:
+            reqs.append((g, None, g.n))
+        else:
+            k = min(256, g.n)
+            reqs.append((g, gg.uniform_sources(g.n, k, 77 + i), k))
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g, _, _ in reqs]
+    srv = bcmi.bc_serve_create(200 << 30)
+    # warm-up: one request of each kind
+    for g, S, _ in reqs[:2]:
+        t = bcmi.bc_serve_submit(srv, g, S, torch.empty(g.n, dtype=torch.float64, device="cuda"))
+        while bcmi.bc_serve_poll(srv, t) is None:
+            time.sleep(0.001)
+    tickets = []
+    t0 = time.perf_counter()
+    for (g, S, _), out, at in zip(reqs, outs, arrive):
+        while time.perf_counter() - t0 < at:
+            pass
+        tickets.append(bcmi.bc_serve_submit(srv, g, S, out))
+    infos = [None] * N
+    pending = set(range(N))
+    last_print = time.perf_counter()
+    while pending:
+        for i in list(pending):
+            inf = bcmi.bc_serve_poll(srv, tickets[i])
+            if inf is not None:
+                infos[i] = inf
+                pending.discard(i)
+        if time.perf_counter() - last_print > 20:
+            print(f"serve: {N - len(pending)}/{N} done", file=sys.stderr, flush=True)
+            last_print = time.perf_counter()
+        time.sleep(0.0005)
+    makespan = time.perf_counter() - t0
+    lat = np.array([i["t_done_ms"] - i["t_submit_ms"] for i in infos])
+    work = sum(k * g.m for g, _, k in reqs)
+    bcmi.bc_serve_destroy(srv)
+    res = {"metric": "served BC requests: throughput and p50/p99 latency", "value": N / makespan,
+           "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 2, "ms_per_step": makespan * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64+f64",
+           "data": "synthetic",
+           "config": {"workload": f"served-poisson{args.serve_rate:g}-rmat8to{args.serve_max_scale}-ef4to16",
+                      "requests": N, "exact_fraction": 0.7, "sampled_k": 256, "graph_pool": 64},
+           "extra": {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                     "mean_ms": float(lat.mean()), "nominal_gteps": work / makespan / 1e9,
+                     "offered_rate_req_s": args.serve_rate}}
+    for g in pool:
         g.free()
     return res
 
@@ -238,11 +336,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat20", "lattice", "batch"])
+    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat20", "lattice", "batch", "serve"])
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="mean arrivals per second")
+    ap.add_argument("--serve-max-scale", type=int, default=14)
     ap.add_argument("--tune", action="store_true", help="autotune launch knobs first (untimed)")
     ap.add_argument("--strategy", default="auto", choices=["auto", "batched", "per-source"])
     ap.add_argument("--knob", action="append", default=[], help="launch knob override, e.g. batch_wg_size=512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-baseline", action="store_true",
+                    help="also time the one-launch-per-source path on a sample of sources")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 2 GiB device-to-device copy first (reference for HBM byte counters)")
@@ -268,6 +371,8 @@ def main():
         del a, b
     if args.workload == "batch":
         res = bench_batch(args, torch, bcmi, gg)
+    elif args.workload == "serve":
+        res = bench_serve(args, torch, bcmi, gg)
     else:
         res = bench_single(args, torch, bcmi, gg)
     print(json.dumps(res), flush=True)

@@ -131,6 +131,68 @@ struct RunArgs {
 int run_sources(const RunArgs& a, const Knobs& k, hipStream_t stream, Graph& g);
 void read_stats(Graph& g, hipStream_t stream, CallStats* out);
 
+// ---- launch plumbing shared by the single-graph, batch and serving paths ------------------
+// One descriptor per (graph, source range) of a launch's work list.
+struct WorkDesc {
+    const uint32_t* row_ptr;
+    const uint32_t* col;
+    double* bc;
+    const uint32_t* sources;   // nullable: local item i is source src_base + i
+    uint32_t* counters;        // nullable: per-descriptor {done, overflowed, levels_max, bad}
+    int32_t n;
+    uint32_t item_begin;       // first work item of this descriptor in the launch
+    uint32_t num_items;
+    uint32_t src_base;
+};
+
+struct LaunchArgs {
+    const WorkDesc* descs;
+    uint32_t ndesc;
+    uint32_t total_items;
+    CallStats* stats;
+    uint32_t hub;
+    uint32_t tpv_max;          // chunk max degree up to which thread-per-vertex is used
+    // global-memory slots
+    VRec* rec;
+    uint32_t* queue;
+    uint32_t* lvl;
+    uint32_t slot_n;
+    uint32_t lds_n;            // LDS path: vertex capacity
+    uint32_t zero_outputs;     // zero each descriptor's BC output and counters first
+    const uint32_t* items_dev; // nullable: number of work items, read on the device
+    uint32_t* head;            // nullable: work counter (default: stats->work_head)
+    // export of one source (inspection entry point)
+    int32_t* ex_dist;
+    uint64_t* ex_sigma;
+    double* ex_sigma_f;
+    double* ex_delta;
+};
+
+// Device-resident per-source state slots of the global-memory path.
+struct SlotPool {
+    VRec* rec = nullptr;
+    uint32_t* queue = nullptr;
+    uint32_t* lvl = nullptr;
+    uint32_t slot_n = 0;
+    int slots = 0;
+};
+
+// One persistent launch over a device-resident work list.
+struct LaunchPlan {
+    bool lds_path = false;
+    int wg = 256;
+    unsigned grid = 0;
+    size_t dyn_lds = 0;
+    LaunchArgs args{};
+};
+
+LaunchPlan make_plan(const Knobs& k, uint32_t max_n, uint32_t items, int device);
+void enqueue_plan(const LaunchPlan& p, hipStream_t st, uint32_t max_n);
+void pool_ensure(SlotPool& p, uint32_t slot_n, int slots, hipStream_t st);
+void pool_free(SlotPool& p);
+size_t pool_bytes(uint32_t slot_n, int slots);
+bool lds_fits(const Knobs& k, uint32_t n, int device);
+
 // ---- tuning (tune.hip) -------------------------------------------------------------------
 Knobs resolve_knobs(Graph& g, const bc_tuning* t);
 Knobs default_knobs(const Graph& g);

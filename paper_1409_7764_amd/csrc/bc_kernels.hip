@@ -34,42 +34,6 @@
 
 namespace bcmi {
 
-// ---- launch-level structures (shared with the host side below) ---------------------------
-struct WorkDesc {
-    const uint32_t* row_ptr;
-    const uint32_t* col;
-    double* bc;
-    const uint32_t* sources;   // nullable: local item i is source i
-    uint32_t* counters;        // nullable: per-descriptor {done, overflowed, levels_max, bad}
-    int32_t n;
-    uint32_t item_begin;
-    uint32_t num_items;
-    uint32_t pad;
-};
-
-struct LaunchArgs {
-    const WorkDesc* descs;
-    uint32_t ndesc;
-    uint32_t total_items;
-    CallStats* stats;
-    uint32_t hub;
-    uint32_t tpv_max;          // chunk max degree up to which thread-per-vertex is used
-    // global-memory slots
-    VRec* rec;
-    uint32_t* queue;
-    uint32_t* lvl;
-    uint32_t slot_n;
-    uint32_t lds_n;            // LDS path: vertex capacity
-    uint32_t zero_outputs;     // zero each descriptor's BC output and counters first
-    const uint32_t* items_dev; // nullable: number of work items, read on the device
-    uint32_t* head;            // nullable: work counter (default: stats->work_head)
-    // export of one source (inspection entry point)
-    int32_t* ex_dist;
-    uint64_t* ex_sigma;
-    double* ex_sigma_f;
-    double* ex_delta;
-};
-
 namespace {
 
 constexpr uint32_t kPiece = 256;     // hub edges per wavefront work piece
@@ -572,7 +536,7 @@ __device__ __forceinline__ bool claim_item(const LaunchArgs& a, Scratch<WG>& L, 
         if (item >= total) return false;
         const WorkDesc& D = a.descs[di];
         const uint32_t local = item - D.item_begin;
-        s = D.sources ? D.sources[local] : local;
+        s = D.sources ? D.sources[local] : D.src_base + local;
         if (s < (uint32_t)D.n && (uint32_t)D.n <= n_cap) return true;
         if (threadIdx.x == 0) {
             atomicAdd(&a.stats->bad_source, 1u);
@@ -714,15 +678,6 @@ int occupancy_blocks(bool lds_path, int wg, size_t dyn_lds) {
     return per_cu;
 }
 
-// Device-resident slot pool for the global-memory path.
-struct SlotPool {
-    VRec* rec = nullptr;
-    uint32_t* queue = nullptr;
-    uint32_t* lvl = nullptr;
-    uint32_t slot_n = 0;
-    int slots = 0;
-};
-
 void pool_free(SlotPool& p) {
     if (p.rec) (void)hipFree(p.rec);
     if (p.queue) (void)hipFree(p.queue);
@@ -748,15 +703,6 @@ void pool_ensure(SlotPool& p, uint32_t slot_n, int slots, hipStream_t st) {
                        p.rec, count);
     BC_HIP_TRY(hipGetLastError());
 }
-
-// Plans one launch over a list of work descriptors (already on the device) and enqueues it.
-struct LaunchPlan {
-    bool lds_path = false;
-    int wg = 256;
-    unsigned grid = 0;
-    size_t dyn_lds = 0;
-    LaunchArgs args{};
-};
 
 void enqueue_plan(const LaunchPlan& p, hipStream_t st, uint32_t max_n) {
     // zero outputs and counters, then the persistent search kernel
@@ -791,13 +737,18 @@ void enqueue_plan(const LaunchPlan& p, hipStream_t st, uint32_t max_n) {
     BC_HIP_TRY(hipGetLastError());
 }
 
+bool lds_fits(const Knobs& k, uint32_t n, int device) {
+    const DevInfo& di = dev_info(device);
+    return k.lds_max_n > 0 && n <= (uint32_t)k.lds_max_n && n <= 65535 &&
+           lds_state_bytes(n) + scratch_bytes(norm_wg(k.wg_size)) <= (size_t)di.lds_per_block;
+}
+
 // Decide path and launch shape for `items` work items over graphs of at most max_n vertices.
 LaunchPlan make_plan(const Knobs& k, uint32_t max_n, uint32_t items, int device) {
     LaunchPlan p;
     const DevInfo& di = dev_info(device);
     p.wg = norm_wg(k.wg_size);
-    p.lds_path = k.lds_max_n > 0 && max_n <= (uint32_t)k.lds_max_n && max_n <= 65535 &&
-                 lds_state_bytes(max_n) + scratch_bytes(p.wg) <= (size_t)di.lds_per_block;
+    p.lds_path = lds_fits(k, max_n, device);
     p.dyn_lds = p.lds_path ? lds_state_bytes(max_n) : 0;
     int per_cu = occupancy_blocks(p.lds_path, p.wg, p.dyn_lds);
     if (per_cu < 1) {
@@ -1045,12 +996,7 @@ static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* b
             bp->outs.push_back(bcs[i]);
         }
         // class 0: LDS-resident graphs, class 1: the rest; each class largest work first
-        const DevInfo& di = dev_info(dev);
-        const int wg = norm_wg(k.wg_size);
-        auto fits_lds = [&](const Graph* g) {
-            return k.lds_max_n > 0 && g->n <= k.lds_max_n && g->n <= 65535 &&
-                   lds_state_bytes((uint32_t)g->n) + scratch_bytes(wg) <= (size_t)di.lds_per_block;
-        };
+        auto fits_lds = [&](const Graph* g) { return lds_fits(k, (uint32_t)g->n, dev); };
         std::vector<int> cls[2];
         for (int i = 0; i < num; ++i) cls[fits_lds(bp->graphs[i]) ? 0 : 1].push_back(i);
         for (auto& v : cls)

@@ -1,9 +1,448 @@
-// Serving loop (continuous batching with HBM-footprint admission).
+// Serving: BC requests on resident graphs, admitted by device-memory footprint and run by
+// continuous batching.
+//
+// A server owns one HIP stream and one scheduler thread.  submit() only records the request
+// (never touches the device).  The scheduler:
+//   1. admits queued requests in arrival order while the summed footprint of admitted
+//      requests stays within the budget (graph CSR+CSC, output, per-source state slots);
+//   2. builds a "tick": round-robin over the admitted requests, each contributes its next
+//      chunk of sources, so a request that arrives while others run joins the next tick and
+//      small requests are not queued behind large ones;
+//   3. launches the tick as one persistent launch per state home (LDS-resident for small
+//      graphs, global-memory slots for the rest) over a work list that mixes requests and
+//      graphs; up to two ticks are queued on the stream so the device never waits for the
+//      host;
+//   4. when a tick's event has fired, requests whose last chunk it held are complete; their
+//      device counters (copied back by the tick itself) fill the poll() record.
 #include "bc_internal.h"
 
-extern "C" {
-bc_status bc_serve_create(size_t, int32_t, bc_server*) { return BC_E_STATE; }
-bc_status bc_serve_submit(bc_server, bc_graph, const uint32_t*, int32_t, double*, uint64_t*) { return BC_E_STATE; }
-bc_status bc_serve_poll(bc_server, uint64_t, bc_info*) { return BC_E_STATE; }
-bc_status bc_serve_destroy(bc_server) { return BC_E_STATE; }
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
+namespace bcmi {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum class RState { Queued, Admitted, Done, Failed };
+
+struct Request {
+    Graph* g = nullptr;
+    std::vector<uint32_t> h_sources;   // sampled requests
+    bool exact = false;
+    uint32_t k = 0;                    // number of sources
+    double* d_bc = nullptr;
+    size_t footprint = 0;
+    bool lds = false;
+    RState state = RState::Queued;
+    uint32_t* d_sources = nullptr;
+    uint32_t* d_counters = nullptr;    // {done, overflowed, levels_max, bad}
+    uint32_t* h_counters = nullptr;    // pinned copy, written by the completing tick
+    uint32_t next = 0;                 // next source index to schedule
+    uint32_t inflight = 0;             // chunks launched but not yet reaped
+    double t_submit = 0, t_start = -1, t_done = -1;
+    std::string error;
+};
+
+struct Chunk {
+    uint64_t ticket;
+    bool last;                         // this chunk completes the request
+};
+
+struct Tick {
+    bool busy = false;
+    hipEvent_t done = nullptr;
+    std::vector<Chunk> chunks;
+    WorkDesc* h_desc = nullptr;        // pinned
+    WorkDesc* d_desc = nullptr;
+    CallStats* d_stats = nullptr;      // one per launch class
+    uint32_t cap = 0;
+};
+
+__global__ void k_zero_f64(double* p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0;
 }
+__global__ void k_zero_small(uint32_t* p, uint32_t n) {
+    if (threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+__global__ void k_zero_stats(CallStats* s, uint32_t count) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(s);
+    for (uint32_t i = threadIdx.x; i < count * (sizeof(CallStats) / 4); i += blockDim.x) w[i] = 0u;
+}
+
+constexpr uint32_t kChunkGlobal = 64;     // sources per chunk on the global-slot path
+constexpr uint32_t kChunkLds = 1024;      // sources per chunk on the LDS-resident path
+constexpr uint32_t kTickDescs = 4096;     // chunks per tick
+
+}  // namespace
+
+struct Server {
+    size_t budget = 0, used = 0;
+    int max_slots = 0;
+    int device = 0;
+    hipStream_t st = nullptr;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stopping = false;
+    uint64_t next_ticket = 1;
+    std::deque<uint64_t> queue;
+    std::vector<uint64_t> active;
+    std::unordered_map<uint64_t, Request> reqs;
+    Clock::time_point t0;
+    Knobs knobs;
+    SlotPool pool;
+    Tick ticks[2];
+    std::string fatal;
+
+    double now_ms() const { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
+
+    size_t footprint(const Graph& g, uint32_t k, bool lds) const {
+        const size_t n = (size_t)g.n, m = g.m;
+        size_t f = 2 * (4 * (n + 1) + 4 * m) + 8 * n;
+        if (!lds) f += (size_t)std::min<uint32_t>(k, kChunkGlobal) * (24 * n + 4);
+        return f;
+    }
+
+    void admit_locked() {
+        while (!queue.empty()) {
+            Request& r = reqs[queue.front()];
+            if (used + r.footprint > budget) break;
+            used += r.footprint;
+            const uint32_t n = (uint32_t)r.g->n;
+            BC_HIP_TRY(hipMalloc((void**)&r.d_counters, 4 * sizeof(uint32_t)));
+            BC_HIP_TRY(hipHostMalloc((void**)&r.h_counters, 4 * sizeof(uint32_t), hipHostMallocDefault));
+            if (!r.exact && r.k) {
+                BC_HIP_TRY(hipMalloc((void**)&r.d_sources, sizeof(uint32_t) * r.k));
+                BC_HIP_TRY(hipMemcpyAsync(r.d_sources, r.h_sources.data(), sizeof(uint32_t) * r.k,
+                                          hipMemcpyHostToDevice, st));
+            }
+            hipLaunchKernelGGL(k_zero_f64, dim3(std::max(1u, std::min<unsigned>((n + 255) / 256, 1024))), dim3(256), 0,
+                               st, r.d_bc, n);
+            hipLaunchKernelGGL(k_zero_small, dim3(1), dim3(64), 0, st, r.d_counters, 4u);
+            BC_HIP_TRY(hipGetLastError());
+            if (r.k == 0) {   // nothing to run: done once the output is zeroed
+                BC_HIP_TRY(hipStreamSynchronize(st));
+                for (int i = 0; i < 4; ++i) r.h_counters[i] = 0;
+                r.state = RState::Done;
+                r.t_start = r.t_done = now_ms();
+                used -= r.footprint;
+                queue.pop_front();
+                continue;
+            }
+            r.state = RState::Admitted;
+            active.push_back(queue.front());
+            queue.pop_front();
+        }
+    }
+
+    bool has_schedulable_locked() const {
+        for (uint64_t t : active) {
+            const Request& r = reqs.at(t);
+            if (r.next < r.k) return true;
+        }
+        return false;
+    }
+
+    // Builds and launches one tick from the admitted requests (lock held).
+    void launch_tick_locked(Tick& tk) {
+        std::vector<WorkDesc> cls[2];     // 0: LDS-resident, 1: global slots
+        std::vector<Chunk> chunks[2];
+        uint32_t items[2] = {0, 0}, maxn[2] = {0, 0};
+        // a tick holds about one round of the persistent grid, so its duration is bounded and a
+        // request arriving meanwhile starts within roughly one source's search time
+        const uint32_t item_cap[2] = {1u << 16, (uint32_t)std::max(1, max_slots)};
+        bool progress = true;
+        while (progress && cls[0].size() + cls[1].size() < kTickDescs) {
+            progress = false;
+            for (uint64_t t : active) {
+                Request& r = reqs[t];
+                if (r.next >= r.k) continue;
+                const int c = r.lds ? 0 : 1;
+                if (items[c] >= item_cap[c]) continue;
+                const uint32_t take = std::min(r.k - r.next, r.lds ? kChunkLds : kChunkGlobal);
+                WorkDesc d{};
+                d.row_ptr = r.g->row_ptr;
+                d.col = r.g->col;
+                d.bc = r.d_bc;
+                d.sources = r.exact ? nullptr : r.d_sources + r.next;
+                d.src_base = r.exact ? r.next : 0u;
+                d.counters = r.d_counters;
+                d.n = r.g->n;
+                d.item_begin = items[c];
+                d.num_items = take;
+                cls[c].push_back(d);
+                r.next += take;
+                r.inflight += 1;
+                if (r.t_start < 0) r.t_start = now_ms();
+                chunks[c].push_back(Chunk{t, r.next >= r.k});
+                items[c] += take;
+                maxn[c] = std::max(maxn[c], (uint32_t)r.g->n);
+                progress = true;
+                if (cls[0].size() + cls[1].size() >= kTickDescs) break;
+            }
+        }
+        const size_t nd = cls[0].size() + cls[1].size();
+        if (nd == 0) return;
+        for (size_t i = 0; i < cls[0].size(); ++i) tk.h_desc[i] = cls[0][i];
+        for (size_t i = 0; i < cls[1].size(); ++i) tk.h_desc[cls[0].size() + i] = cls[1][i];
+        BC_HIP_TRY(hipMemcpyAsync(tk.d_desc, tk.h_desc, sizeof(WorkDesc) * nd, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, st, tk.d_stats, 2u);
+        BC_HIP_TRY(hipGetLastError());
+        for (int c = 0; c < 2; ++c) {
+            if (cls[c].empty()) continue;
+            Knobs k = knobs;
+            if (c == 1) {
+                k.lds_max_n = -1;
+                k.teams = max_slots;
+            }
+            LaunchPlan p = make_plan(k, maxn[c], items[c], device);
+            if (!p.lds_path) {
+                if (!pool.rec || pool.slot_n < maxn[c] || pool.slots < (int)p.grid) {
+                    pool_ensure(pool, std::max(maxn[c], pool.slot_n), std::max<int>(p.grid, pool.slots), st);
+                }
+                p.args.rec = pool.rec;
+                p.args.queue = pool.queue;
+                p.args.lvl = pool.lvl;
+                p.args.slot_n = pool.slot_n;
+            }
+            p.args.descs = tk.d_desc + (c == 0 ? 0 : cls[0].size());
+            p.args.ndesc = (uint32_t)cls[c].size();
+            p.args.total_items = items[c];
+            p.args.stats = tk.d_stats + c;
+            p.args.zero_outputs = 0;   // outputs were zeroed at admission; requests span ticks
+            enqueue_plan(p, st, 0);
+        }
+        tk.chunks.clear();
+        for (int c = 0; c < 2; ++c)
+            for (const Chunk& ch : chunks[c]) {
+                tk.chunks.push_back(ch);
+                if (ch.last) {
+                    Request& r = reqs[ch.ticket];
+                    BC_HIP_TRY(hipMemcpyAsync(r.h_counters, r.d_counters, 4 * sizeof(uint32_t),
+                                              hipMemcpyDeviceToHost, st));
+                }
+            }
+        BC_HIP_TRY(hipEventRecord(tk.done, st));
+        tk.busy = true;
+    }
+
+    void reap_locked(Tick& tk) {
+        const double t = now_ms();
+        for (const Chunk& ch : tk.chunks) {
+            auto it = reqs.find(ch.ticket);
+            if (it == reqs.end()) continue;
+            Request& r = it->second;
+            r.inflight -= 1;
+            if (r.inflight == 0 && r.next >= r.k && r.state == RState::Admitted) {
+                r.state = RState::Done;
+                r.t_done = t;
+                used -= r.footprint;
+                if (r.d_sources) (void)hipFree(r.d_sources);
+                r.d_sources = nullptr;
+                active.erase(std::find(active.begin(), active.end(), ch.ticket));
+            }
+        }
+        tk.chunks.clear();
+        tk.busy = false;
+    }
+
+    void fail_all_locked(const std::string& msg) {
+        fatal = msg;
+        for (auto& kv : reqs)
+            if (kv.second.state == RState::Queued || kv.second.state == RState::Admitted) {
+                kv.second.state = RState::Failed;
+                kv.second.error = msg;
+            }
+        queue.clear();
+        active.clear();
+    }
+
+    void loop() {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            try {
+                bool worked = false;
+                for (Tick& tk : ticks)
+                    if (tk.busy && hipEventQuery(tk.done) == hipSuccess) {
+                        reap_locked(tk);
+                        worked = true;
+                    }
+                if (!fatal.empty()) {
+                    // nothing more runs after a device failure
+                } else {
+                    admit_locked();
+                    for (Tick& tk : ticks)
+                        if (!tk.busy && has_schedulable_locked()) {
+                            launch_tick_locked(tk);
+                            worked = true;
+                        }
+                }
+                const bool idle = !ticks[0].busy && !ticks[1].busy;
+                if (stopping && idle && (active.empty() || !fatal.empty())) break;
+                if (!worked) {
+                    if (idle && !has_schedulable_locked() && queue.empty()) cv.wait(lk);
+                    else cv.wait_for(lk, std::chrono::microseconds(50));
+                }
+            } catch (const Error& e) {
+                fail_all_locked(e.msg);
+            } catch (const std::exception& e) {
+                fail_all_locked(e.what());
+            }
+        }
+    }
+};
+
+}  // namespace bcmi
+
+using namespace bcmi;
+
+namespace {
+template <class F>
+bc_status guarded_serve(F&& body) {
+    try {
+        clear_error();
+        return body();
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return BC_E_HIP;
+    } catch (...) {
+        set_error("unknown failure");
+        return BC_E_HIP;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+bc_status bc_serve_create(size_t hbm_budget_bytes, int32_t max_slots, bc_server* out) {
+    return guarded_serve([&]() -> bc_status {
+        BC_REQUIRE(out != nullptr, BC_E_INVAL, "null output handle");
+        BC_REQUIRE(hbm_budget_bytes > 0, BC_E_INVAL, "budget must be > 0");
+        BC_REQUIRE(max_slots >= 0, BC_E_INVAL, "max_slots must be >= 0");
+        Server* s = new Server();
+        try {
+            BC_HIP_TRY(hipGetDevice(&s->device));
+            s->budget = hbm_budget_bytes;
+            s->knobs = Knobs{};
+            s->knobs.hub = 64;
+            const DevInfo& di = dev_info(s->device);
+            s->max_slots = max_slots > 0 ? max_slots : di.cus * 4;
+            BC_HIP_TRY(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+            for (Tick& tk : s->ticks) {
+                BC_HIP_TRY(hipEventCreateWithFlags(&tk.done, hipEventDisableTiming));
+                BC_HIP_TRY(hipHostMalloc((void**)&tk.h_desc, sizeof(WorkDesc) * kTickDescs, hipHostMallocDefault));
+                BC_HIP_TRY(hipMalloc((void**)&tk.d_desc, sizeof(WorkDesc) * kTickDescs));
+                BC_HIP_TRY(hipMalloc((void**)&tk.d_stats, sizeof(CallStats) * 2));
+                tk.cap = kTickDescs;
+            }
+            s->t0 = Clock::now();
+            s->th = std::thread([s] { s->loop(); });
+        } catch (...) {
+            delete s;
+            throw;
+        }
+        *out = reinterpret_cast<bc_server>(s);
+        return BC_OK;
+    });
+}
+
+bc_status bc_serve_submit(bc_server sh, bc_graph gh, const uint32_t* h_sources, int32_t k, double* d_bc,
+                          uint64_t* ticket) {
+    return guarded_serve([&]() -> bc_status {
+        BC_REQUIRE(sh && gh && d_bc && ticket, BC_E_INVAL, "null argument");
+        Server* s = reinterpret_cast<Server*>(sh);
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        BC_REQUIRE(g->device == s->device, BC_E_INVAL, "graph lives on another device");
+        BC_REQUIRE(h_sources == nullptr || k >= 0, BC_E_INVAL, "k must be >= 0");
+        Request r;
+        r.g = g;
+        r.exact = h_sources == nullptr;
+        r.k = r.exact ? (uint32_t)g->n : (uint32_t)k;
+        if (!r.exact) {
+            r.h_sources.assign(h_sources, h_sources + k);
+            for (uint32_t x : r.h_sources) BC_REQUIRE(x < (uint32_t)g->n, BC_E_RANGE, "source id >= n");
+        }
+        r.d_bc = d_bc;
+        r.lds = lds_fits(s->knobs, (uint32_t)g->n, s->device);
+        r.footprint = s->footprint(*g, r.k, r.lds);
+        BC_REQUIRE(r.footprint <= s->budget, BC_E_NOMEM, "request footprint exceeds the server budget");
+        std::lock_guard<std::mutex> lk(s->mu);
+        BC_REQUIRE(!s->stopping, BC_E_STATE, "server is stopping");
+        BC_REQUIRE(s->fatal.empty(), BC_E_HIP, "server failed: " + s->fatal);
+        r.t_submit = s->now_ms();
+        const uint64_t t = s->next_ticket++;
+        s->reqs.emplace(t, std::move(r));
+        s->queue.push_back(t);
+        *ticket = t;
+        s->cv.notify_all();
+        return BC_OK;
+    });
+}
+
+bc_status bc_serve_poll(bc_server sh, uint64_t ticket, bc_info* info) {
+    return guarded_serve([&]() -> bc_status {
+        BC_REQUIRE(sh != nullptr, BC_E_INVAL, "null server");
+        Server* s = reinterpret_cast<Server*>(sh);
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        BC_REQUIRE(it != s->reqs.end(), BC_E_STATE, "unknown ticket");
+        const Request& r = it->second;
+        if (r.state == RState::Failed) throw Error{BC_E_HIP, "request failed: " + r.error};
+        if (r.state != RState::Done) return BC_PENDING;
+        if (info) {
+            bc_info o{};
+            o.n_sources = r.h_counters[0];
+            o.n_sigma_fp64_fallback = r.h_counters[1];
+            o.levels_max = r.h_counters[2];
+            o.path = r.lds ? 1u : 0u;
+            o.kernel_ms = r.t_done - r.t_start;
+            o.t_submit_ms = r.t_submit;
+            o.t_start_ms = r.t_start;
+            o.t_done_ms = r.t_done;
+            *info = o;
+        }
+        return BC_OK;
+    });
+}
+
+bc_status bc_serve_destroy(bc_server sh) {
+    return guarded_serve([&]() -> bc_status {
+        BC_REQUIRE(sh != nullptr, BC_E_INVAL, "null server");
+        Server* s = reinterpret_cast<Server*>(sh);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stopping = true;
+            for (uint64_t t : s->queue) s->reqs[t].state = RState::Failed;   // never admitted: cancelled
+            s->queue.clear();
+            s->cv.notify_all();
+        }
+        if (s->th.joinable()) s->th.join();
+        (void)hipStreamSynchronize(s->st);
+        for (auto& kv : s->reqs) {
+            if (kv.second.d_sources) (void)hipFree(kv.second.d_sources);
+            if (kv.second.d_counters) (void)hipFree(kv.second.d_counters);
+            if (kv.second.h_counters) (void)hipHostFree(kv.second.h_counters);
+        }
+        for (Tick& tk : s->ticks) {
+            if (tk.done) (void)hipEventDestroy(tk.done);
+            if (tk.h_desc) (void)hipHostFree(tk.h_desc);
+            if (tk.d_desc) (void)hipFree(tk.d_desc);
+            if (tk.d_stats) (void)hipFree(tk.d_stats);
+        }
+        pool_free(s->pool);
+        (void)hipStreamDestroy(s->st);
+        delete s;
+        return BC_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+"""Serving and autotuning through the C ABI (GPU only): every request's result is the same
+alone and in the mix (1e-9), and matches the oracle; requests that arrive while others run
+overlap with them on the device; admission by footprint holds requests back or rejects them."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1409_7764_amd import graphgen as gg
+
+from helpers import rel_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bc():
+    import torch
+    from paper_1409_7764_amd import bcmi
+    assert torch.cuda.is_available()
+    bcmi.lib()
+    return bcmi
+
+
+def wait(bc, srv, ticket, timeout=120.0):
+    t0 = time.time()
+    while True:
+        info = bc.bc_serve_poll(srv, ticket)
+        if info is not None:
+            return info
+        assert time.time() - t0 < timeout, "request did not finish"
+        time.sleep(0.0005)
+
+
+def footprint(n, m, k, lds):
+    f = 2 * (4 * (n + 1) + 4 * m) + 8 * n
+    if not lds:
+        f += min(k, 64) * (24 * n + 4)
+    return f
+
+
+def test_serve_alone_equals_mix(bc):
+    import torch
+    specs = [(6, 8, 1), (9, 4, 2), (12, 16, 3), (13, 8, 4), (14, 4, 5)]
+    graphs, coo = [], []
+    for sc, ef, seed in specs:
+        n, u, v = gg.rmat(sc, ef, seed)
+        graphs.append(bc.bc_build_csr(n, u, v))
+        coo.append((n, u, v))
+    rng = np.random.default_rng(0)
+    reqs = []
+    for i in range(24):
+        gi = int(rng.integers(0, len(graphs)))
+        n = graphs[gi].n
+        if rng.random() < 0.5 and n <= 4096:
+            reqs.append((gi, None))
+        else:
+            reqs.append((gi, gg.uniform_sources(n, int(rng.integers(1, 300)), 100 + i)))
+    alone = []
+    for gi, S in reqs:
+        g = graphs[gi]
+        out = bc.bc_exact(g) if S is None else bc.bc_sampled(g, S)
+        alone.append(out.cpu().numpy())
+    srv = bc.bc_serve_create(64 << 30)
+    outs = [torch.full((graphs[gi].n,), -1.0, dtype=torch.float64, device="cuda") for gi, _ in reqs]
+    tickets = [bc.bc_serve_submit(srv, graphs[gi], S, out) for (gi, S), out in zip(reqs, outs)]
+    infos = [wait(bc, srv, t) for t in tickets]
+    for i, ((gi, S), out, inf) in enumerate(zip(reqs, outs, infos)):
+        got = out.cpu().numpy()
+        rel_close(got, alone[i], what=f"request {i} alone vs mix")
+        k = graphs[gi].n if S is None else len(S)
+        assert inf["n_sources"] == k
+        assert inf["t_submit_ms"] <= inf["t_start_ms"] <= inf["t_done_ms"]
+    # oracle on a few of them
+    for i in [0, 1, 2, 3]:
+        gi, S = reqs[i]
+        n, u, v = coo[gi]
+        want, _, _ = oracle.bc(oracle.Graph(n, u, v), S)
+        rel_close(outs[i].cpu().numpy(), want, what=f"request {i} vs oracle")
+    bc.bc_serve_destroy(srv)
+    for g in graphs:
+        g.free()
+
+
+def test_serve_overlap_and_continuous_batching(bc):
+    import torch
+    n, u, v = gg.rmat(15, 16, 7)
+    big = bc.bc_build_csr(n, u, v)
+    n2, u2, v2 = gg.rmat(8, 8, 8)
+    small = bc.bc_build_csr(n2, u2, v2)
+    srv = bc.bc_serve_create(64 << 30)
+    out_a = torch.empty(big.n, dtype=torch.float64, device="cuda")
+    out_b = torch.empty(small.n, dtype=torch.float64, device="cuda")
+    SA = gg.uniform_sources(big.n, 8192, 1)
+    ta = bc.bc_serve_submit(srv, big, SA, out_a)   # spans many ticks
+    time.sleep(0.005)
+    tb = bc.bc_serve_submit(srv, small, None, out_b)
+    ib = wait(bc, srv, tb)
+    ia = wait(bc, srv, ta)
+    # B arrived while A was on the device, joined a tick before A finished, and finished first
+    assert ib["t_submit_ms"] < ia["t_done_ms"]
+    assert ib["t_start_ms"] < ia["t_done_ms"]
+    assert ib["t_done_ms"] < ia["t_done_ms"]
+    want_b, _, _ = oracle.bc(oracle.Graph(n2, u2, v2))
+    rel_close(out_b.cpu().numpy(), want_b)
+    rel_close(out_a.cpu().numpy(), bc.bc_sampled(big, SA).cpu().numpy())
+    bc.bc_serve_destroy(srv)
+    big.free()
+    small.free()
+
+
+def test_serve_admission_budget(bc):
+    import torch
+    n, u, v = gg.rmat(13, 8, 9)
+    g = bc.bc_build_csr(n, u, v)
+    f = footprint(g.n, g.m, 512, lds=False)
+    srv = bc.bc_serve_create(int(1.5 * f))       # room for one request at a time
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    S = [gg.uniform_sources(g.n, 512, 20 + i) for i in range(3)]
+    ts = [bc.bc_serve_submit(srv, g, S[i], outs[i]) for i in range(3)]
+    infos = [wait(bc, srv, t) for t in ts]
+    for a, b in zip(infos, infos[1:]):
+        assert b["t_start_ms"] >= a["t_done_ms"]       # admitted only after the previous one left
+    for i in range(3):
+        rel_close(outs[i].cpu().numpy(), bc.bc_sampled(g, S[i]).cpu().numpy())
+    tiny = bc.bc_serve_create(f // 2)
+    with pytest.raises(bc.BcError) as e:       # larger than the whole budget
+        bc.bc_serve_submit(tiny, g, None, outs[0])
+    assert e.value.code == bc.BC_E_NOMEM
+    bc.bc_serve_destroy(tiny)
+    with pytest.raises(bc.BcError) as e:
+        bc.bc_serve_submit(srv, g, np.array([g.n], np.uint32), outs[0])
+    assert e.value.code == bc.BC_E_RANGE
+    bc.bc_serve_destroy(srv)
+    g.free()
+
+
+def test_serve_destroy_with_work_queued(bc):
+    import torch
+    n, u, v = gg.rmat(12, 8, 11)
+    g = bc.bc_build_csr(n, u, v)
+    srv = bc.bc_serve_create(footprint(g.n, g.m, 64, False) * 2)
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in range(8)]
+    for i in range(8):
+        bc.bc_serve_submit(srv, g, gg.uniform_sources(g.n, 64, i), outs[i])
+    bc.bc_serve_destroy(srv)      # cancels what was not admitted, finishes what runs
+    g.free()
+
+
+def test_autotune_keeps_results(bc):
+    n, u, v = gg.rmat(14, 16, 12)
+    g = bc.bc_build_csr(n, u, v)
+    S = gg.uniform_sources(n, 200, 3)
+    before = bc.bc_sampled(g, S).cpu().numpy()
+    t = bc.bc_tune(g)
+    assert t["wg_size"] in (64, 128, 256, 512, 1024)
+    after, info = bc.bc_sampled(g, S, tuning=bc.tuning(**t), info=True)
+    rel_close(after.cpu().numpy(), before, 1e-12)
+    n2, u2, v2 = gg.rmat(9, 8, 12)
+    g2 = bc.bc_build_csr(n2, u2, v2)
+    t2 = bc.bc_tune(g2)
+    assert t2["batched"] == -1          # small graphs stay on the LDS-resident path
+    want, _, _ = oracle.bc(oracle.Graph(n2, u2, v2))
+    rel_close(bc.bc_exact(g2).cpu().numpy(), want)
+    g.free()
+    g2.free()
