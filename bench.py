@@ -238,18 +238,20 @@ def bench_batch(args, torch, bcmi, gg):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     nominal = sum(g.n * g.m for g in graphs)
-    # the same work as one exact launch per graph
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for g, o in zip(graphs, outs):
-        bcmi.bc_exact(g, out=o)
-    torch.cuda.synchronize()
-    per_graph_ms = (time.perf_counter() - t0) * 1e3
-    # one launch per source, timed on a sample and scaled to every source
-    sample_ms = []
-    for g in graphs[:16]:
-        sample_ms.append(one_source_per_launch_ms(bcmi, torch, g, np.arange(g.n), 32))
-    per_source_ms = float(np.mean(sample_ms)) * sum(g.n for g in graphs)
+    per_graph_ms = per_source_ms = float("nan")
+    if not args.skip_compare:
+        # the same work as one exact launch per graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for g, o in zip(graphs, outs):
+            bcmi.bc_exact(g, out=o)
+        torch.cuda.synchronize()
+        per_graph_ms = (time.perf_counter() - t0) * 1e3
+        # one launch per source, timed on a sample and scaled to every source
+        sample_ms = []
+        for g in graphs[:16]:
+            sample_ms.append(one_source_per_launch_ms(bcmi, torch, g, np.arange(g.n), 32))
+        per_source_ms = float(np.mean(sample_ms)) * sum(g.n for g in graphs)
     res = {"metric": "GTEPS (sources x edges / s), nominal, batched exact BC", "value": nominal / (ms / 1e3) / 1e9,
            "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -344,6 +346,8 @@ def main():
     ap.add_argument("--strategy", default="auto", choices=["auto", "batched", "per-source"])
     ap.add_argument("--knob", action="append", default=[], help="launch knob override, e.g. batch_wg_size=512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-compare", action="store_true",
+                    help="batch workload: skip the one-launch-per-graph / per-source comparisons")
     ap.add_argument("--plain-baseline", action="store_true",
                     help="also time the one-launch-per-source path on a sample of sources")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle sample")
