@@ -102,9 +102,15 @@ struct StreamTimer {
     }
 };
 
+void graph_discard_batched_state(Graph& g);
+
 static void fill_info(Graph& g, hipStream_t st, int path, double ms, uint32_t expected, bc_info* info) {
     CallStats cs;
     read_stats(g, st, &cs);
+    if (cs.pad[0]) {
+        graph_discard_batched_state(g);
+        throw Error{BC_E_HIP, "batched kernel: a team of workgroups stopped waiting at a level barrier"};
+    }
     BC_REQUIRE(cs.bad_source == 0, BC_E_RANGE, "a source id is >= n");
     BC_REQUIRE(cs.n_done == expected, BC_E_HIP, "not every source completed");
     bc_info out{};

@@ -60,7 +60,7 @@ struct CallStats {
     uint32_t levels_max;     // deepest search
     uint32_t bad_source;     // sources with id >= n (skipped)
     uint32_t work_head2;     // work counter of a follow-up launch in the same call
-    uint32_t pad[2];
+    uint32_t pad[2];         // pad[0]: a batched team gave up waiting at a barrier
     uint64_t reached;        // sum over sources of reached vertices (source included)
     uint64_t examined;       // sum over sources of out-edges of reached vertices
     uint64_t dag_edges;      // sum over sources of shortest-path DAG edges
@@ -72,7 +72,7 @@ struct CallStats {
 // Launch knobs after defaults / tuning are applied.
 struct Knobs {
     int wg_size = 256;
-    int team = 1;                // workgroups per source
+    int team = 0;                // batched path: workgroups per batch (0 = from the batch count)
     int teams = 0;               // concurrent sources; 0 = fill the device
     int hub = 32;                // wavefront-per-vertex threshold
     int lds_max_n = 4096;

@@ -802,7 +802,7 @@ struct MsbPool;
 MsbPool* msb_pool_new();
 void msb_pool_delete(MsbPool* p);
 void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
-                     int wg, int slots_cap, hipStream_t st,
+                     int wg, int team_knob, int slots_cap, hipStream_t st,
                      void (*retry_launch)(void*, const uint32_t*, const uint32_t*, uint32_t, hipStream_t),
                      void* retry_ctx);
 
@@ -920,8 +920,16 @@ int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     z.grid = 0;
     enqueue_plan(z, st, (uint32_t)g.n);
     RetryCtx rc{&g, &gs, k, ra.bc};
-    run_msb_enqueue(*gs.msb, g, ra.sources, ra.num_items, ra.bc, g.stats, k.batch_wg, k.teams, st, retry_launch, &rc);
+    run_msb_enqueue(*gs.msb, g, ra.sources, ra.num_items, ra.bc, g.stats, k.batch_wg, k.team, k.teams, st,
+                    retry_launch, &rc);
     return 2;
+}
+
+void msb_pool_discard(MsbPool* p);
+
+// Drops the batched path's state after a team gave up on a barrier (the state is dirty).
+void graph_discard_batched_state(Graph& g) {
+    if (g.slots) msb_pool_discard(reinterpret_cast<GraphScratch*>(g.slots)->msb);
 }
 
 void read_stats(Graph& g, hipStream_t st, CallStats* out) {

@@ -34,6 +34,20 @@
 
 namespace bcmi {
 
+// Per-team control block in global memory (a team = the workgroups sharing one batch).
+struct alignas(128) TeamCtl {
+    uint32_t bar_count;
+    uint32_t bar_gen;
+    uint32_t batch;          // batch being run
+    uint32_t tail;           // level-list append position
+    uint32_t cc;             // chunk claim counter of the current phase
+    uint32_t abort;          // a barrier wait ran out: every member leaves
+    uint32_t sdeg[2];        // out-degree sum of a level (double-buffered by level parity)
+    uint64_t maxsig[2];      // largest count met while expanding a level (by parity)
+    uint64_t ovf;            // sources whose counts carried out of 64 bits
+    uint32_t pad[16];
+};
+
 struct MsbArgs {
     const uint32_t* row_ptr;
     const uint32_t* col;
@@ -43,23 +57,27 @@ struct MsbArgs {
     uint32_t* retry;             // sources handed to the per-source kernel
     uint32_t* retry_count;
     CallStats* stats;
-    uint64_t* seen;              // [slots][n]
-    uint64_t* nxt;               // [slots][n]
-    uint64_t* sig;               // [slots][n][64]
-    double* hacc;                // [slots][hub_rows][64]
-    uint32_t* lst_v;             // [slots][cap]
-    uint64_t* lst_m;             // [slots][cap]
-    uint32_t* lvl;               // [slots][max_levels + 2]
+    TeamCtl* ctl;                // [teams]
+    uint64_t* seen;              // [teams][n]
+    uint64_t* nxt;               // [teams][n]
+    uint64_t* sig;               // [teams][n][64]
+    double* hacc;                // [workgroups][hub_rows][64]
+    uint32_t* lst_v;             // [teams][cap]
+    uint64_t* lst_m;             // [teams][cap]
+    uint32_t* lvl;               // [teams][max_levels + 2]
     int32_t n;
     uint32_t cap;
     uint32_t max_levels;
     uint32_t hub_rows;
+    uint32_t team_size;          // workgroups per team; 0 = as many as the batch count allows
+    uint32_t pool_teams;         // team slots in the pool
     double in2;                  // (largest in-degree)^2
 };
 
 namespace {
 
-constexpr double kSafeSigma = 1.8e19;   // below 2^64 = 1.8447e19
+constexpr double kSafeSigma = 1.8e19;      // below 2^64 = 1.8447e19
+constexpr uint32_t kSpinLimit = 1u << 22;  // barrier polls (about 1 us each) before a team gives up
 
 __device__ __forceinline__ unsigned lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -93,10 +111,13 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     }
     return x;
 }
-__device__ __forceinline__ void level_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+template <class T>
+__device__ __forceinline__ T ld_acq(T* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void st_rel(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int WG>
@@ -112,12 +133,46 @@ struct MsbLds {
     uint32_t sw[WG / 64][64];   // per wavefront: compacted (successor, source mask) pairs of a unit
     uint64_t sm[WG / 64][64];
     uint32_t nhub;
-    uint32_t tail;          // level-list append position
-    uint32_t batch;
-    uint32_t sdeg;          // out-degree sum of the current level
-    uint64_t ovf;           // sources whose counts carried out of 64 bits
-    uint64_t maxsig;        // largest count on the current level
+    uint32_t chunk;
+    uint32_t ok;            // 0 once the team gave up on a barrier
+    uint64_t ovf;           // this workgroup's carries, flushed to the team at level ends
+    uint64_t maxsig;        // this workgroup's largest count on the current level
 };
+
+// Team-wide barrier over the workgroups of one team, with a bounded wait.  Makes every
+// member's global writes visible to every member.  Returns false if the team has given up.
+template <int WG>
+__device__ bool team_sync(MsbLds<WG>& L, TeamCtl* c, uint32_t W, CallStats* stats) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (W > 1 && threadIdx.x == 0) {
+        uint32_t ok = 1;
+        const uint32_t gen = ld_acq(&c->bar_gen);
+        const uint32_t arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == W - 1) {
+            __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            uint32_t spins = 0;
+            while (ld_acq(&c->bar_gen) == gen) {
+                if (ld_acq(&c->abort) || ++spins > kSpinLimit) {
+                    st_rel(&c->abort, 1u);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        if (ld_acq(&c->abort)) ok = 0;
+        if (!ok) atomicOr(&stats->pad[0], 1u);
+        L.ok = ok;
+    } else if (threadIdx.x == 0) {
+        L.ok = 1;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return L.ok != 0u;
+}
 
 template <int WG>
 __device__ __forceinline__ uint32_t find_owner(const uint32_t* a, uint32_t p) {
@@ -148,14 +203,14 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total,
     return before + incl - x;
 }
 
-template <int WG>
-__device__ __forceinline__ void append(MsbLds<WG>& L, uint32_t* lv, bool fresh, uint32_t w) {
+// wavefront-aggregated append of fresh vertices to the team's level list
+__device__ __forceinline__ void append(TeamCtl* c, uint32_t* lv, bool fresh, uint32_t w) {
     const uint64_t mask = __ballot(fresh);
     if (mask) {
         const unsigned lane = lane_id();
         const unsigned leader = __builtin_ctzll(mask);
         uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&L.tail, (uint32_t)__builtin_popcountll(mask));
+        if (lane == leader) base = atomicAdd(&c->tail, (uint32_t)__builtin_popcountll(mask));
         base = __shfl(base, leader, 64);
         if (fresh) lv[base + (uint32_t)__builtin_popcountll(mask & ((1ull << lane) - 1ull))] = w;
     }
@@ -163,25 +218,25 @@ __device__ __forceinline__ void append(MsbLds<WG>& L, uint32_t* lv, bool fresh, 
 
 // forward work unit: up to 64 out-edges [e0, e1) of the level-d entry (v, f)
 template <int WG>
-__device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, uint64_t* seen, uint64_t* nxt,
+__device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, TeamCtl* c, uint64_t* seen, uint64_t* nxt,
                                          uint64_t* sig, uint32_t* lv, uint32_t v, uint64_t f, uint32_t e0,
                                          uint32_t e1, bool safe) {
     const unsigned lane = lane_id();
     const bool act = (f >> lane) & 1ull;
-    const uint64_t sv = act ? sig[(size_t)v * 64 + lane] : 0ull;
-    const uint64_t mx = wave_max64(sv);
-    if (lane == 0 && mx > L.maxsig) atomicMax((unsigned long long*)&L.maxsig, (unsigned long long)mx);
     const uint32_t e = e0 + lane;
     const bool ok = e < e1;
-    uint32_t w = 0;
+    // independent loads first: this vertex's counts and the unit's successors
+    const uint64_t sv = act ? sig[(size_t)v * 64 + lane] : 0ull;
+    const uint32_t w = ok ? a.col[e] : 0u;
     uint64_t dag = 0;
     bool fresh = false;
     if (ok) {
-        w = a.col[e];
         dag = f & ~seen[w];
         if (dag) fresh = atomicOr((unsigned long long*)&nxt[w], (unsigned long long)dag) == 0ull;
     }
-    append<WG>(L, lv, fresh, w);
+    const uint64_t mx = wave_max64(sv);
+    if (lane == 0 && mx > L.maxsig) atomicMax((unsigned long long*)&L.maxsig, (unsigned long long)mx);
+    append(c, lv, fresh, w);
     // phase B, lane per source: the unit's DAG edges, compacted in LDS, one row update each
     const uint64_t bal = __ballot(dag != 0ull);
     const uint32_t cnt = (uint32_t)__builtin_popcountll(bal);
@@ -237,64 +292,105 @@ __device__ __forceinline__ void finish_entry(const MsbArgs& a, uint64_t* sig, ui
     }
 }
 
+// Claims the next chunk of the current phase for this workgroup (team-wide counter).
+template <int WG>
+__device__ __forceinline__ uint32_t claim_chunk(MsbLds<WG>& L, TeamCtl* c) {
+    if (threadIdx.x == 0) L.chunk = atomicAdd(&c->cc, 1u);
+    __syncthreads();
+    const uint32_t ch = L.chunk;
+    __syncthreads();
+    return ch;
+}
+
 template <int WG>
 __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     __shared__ MsbLds<WG> L;
     const unsigned tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
     constexpr unsigned NW = WG / 64;
-    const size_t n = (size_t)a.n;
-    uint64_t* seen = a.seen + (size_t)blockIdx.x * n;
-    uint64_t* nxt = a.nxt + (size_t)blockIdx.x * n;
-    uint64_t* sig = a.sig + (size_t)blockIdx.x * n * 64;
-    double* hacc = a.hacc + (size_t)blockIdx.x * a.hub_rows * 64;
-    uint32_t* lv = a.lst_v + (size_t)blockIdx.x * a.cap;
-    uint64_t* lm = a.lst_m + (size_t)blockIdx.x * a.cap;
-    uint32_t* lvl = a.lvl + (size_t)blockIdx.x * (a.max_levels + 2);
     const uint32_t total = *a.plan_count;
     const uint32_t nbatch = (total + 63) / 64;
-    // per-thread work counters, reduced once at the end
+    // Team size, chosen on the device from the batch count: the grid is split into at most
+    // min(batches, pool slots) teams.  With 8-way round-robin dispatch, workgroups b, b+8,
+    // b+16, ... share an XCD; when W divides that stride group, a team is W of them, so its
+    // batch state stays behind one L2.
+    const uint32_t want = max(1u, min(nbatch, a.pool_teams));
+    uint32_t W = a.team_size ? a.team_size : max(1u, min(32u, gridDim.x / want));
+    W = min(W, gridDim.x);
+    const uint32_t per_xcd = gridDim.x / 8;
+    const bool xcd = gridDim.x % 8 == 0 && per_xcd % W == 0;
+    uint32_t team, member;
+    if (xcd) {
+        const uint32_t x = blockIdx.x % 8, l = blockIdx.x / 8;
+        team = x * (per_xcd / W) + l / W;
+        member = l % W;
+    } else {
+        team = blockIdx.x / W;
+        member = blockIdx.x % W;
+    }
+    if (team >= a.pool_teams || team >= (gridDim.x / W)) return;   // no state slot for this workgroup
+    const bool leader = member == 0;
+    TeamCtl* ctl = a.ctl + team;
+    const size_t n = (size_t)a.n;
+    uint64_t* seen = a.seen + (size_t)team * n;
+    uint64_t* nxt = a.nxt + (size_t)team * n;
+    uint64_t* sig = a.sig + (size_t)team * n * 64;
+    double* hacc = a.hacc + (size_t)blockIdx.x * a.hub_rows * 64;
+    uint32_t* lv = a.lst_v + (size_t)team * a.cap;
+    uint64_t* lm = a.lst_m + (size_t)team * a.cap;
+    uint32_t* lvl = a.lvl + (size_t)team * (a.max_levels + 2);
+    const uint32_t gtid = member * WG + tid, gthreads = W * WG;
+    const uint32_t gwave = member * NW + wave, gwaves = W * NW;
     uint32_t reached = 0, dagc = 0, entries = 0;
     uint64_t examined = 0, visits = 0;
     uint32_t n_done = 0, levels_max = 0;
 
+    if (tid == 0) {
+        L.nhub = 0;
+        L.ovf = 0;
+        L.maxsig = 0;
+    }
     for (;;) {
-        if (tid == 0) L.batch = atomicAdd(&a.stats->work_head, 1u);
-        __syncthreads();
-        const uint32_t b = L.batch;
-        __syncthreads();
+        if (leader && tid == 0) {
+            ctl->batch = atomicAdd(&a.stats->work_head, 1u);
+            ctl->tail = 0;
+            ctl->cc = 0;
+            ctl->ovf = 0;
+            ctl->sdeg[0] = ctl->sdeg[1] = 0;
+            ctl->maxsig[0] = ctl->maxsig[1] = 0;
+        }
+        if (!team_sync(L, ctl, W, a.stats)) break;
+        const uint32_t b = ld_acq(&ctl->batch);
         if (b >= nbatch) break;
         const uint32_t base = b * 64;
         const uint32_t nl = min(64u, total - base);
         const uint64_t lanes = nl == 64 ? ~0ull : ((1ull << nl) - 1ull);
         const uint32_t my_src = lane < nl ? a.plan[base + lane] : 0xffffffffu;
-        if (tid == 0) {
-            L.tail = 0;
-            L.ovf = 0;
-            L.maxsig = 1;
-            L.nhub = 0;
-        }
-        __syncthreads();
-        if (wave == 0) {   // level 0: the sources themselves
+        if (leader && wave == 0) {   // level 0: the sources themselves
             bool fresh = false;
             if (lane < nl) {
                 fresh = atomicOr((unsigned long long*)&nxt[my_src], (unsigned long long)(1ull << lane)) == 0ull;
                 sig[(size_t)my_src * 64 + lane] = 1ull;
             }
-            append<WG>(L, lv, fresh, my_src);
+            append(ctl, lv, fresh, my_src);
         }
         // ---------------- forward sweep ----------------
-        uint32_t lo = 0;
-        uint32_t d = 0;
-        bool stopped = false;     // every thread takes the same decision from the same values
-        uint64_t max_prev = 1;    // largest count on level d-1
+        uint32_t lo = 0, d = 0;
+        bool stopped = false;       // every thread takes the same decision from the same values
+        bool aborted = false;
         for (;;) {
-            level_barrier();
-            const uint32_t hi = L.tail;
-            if (tid == 0) L.sdeg = 0;
-            __syncthreads();
+            if (!team_sync(L, ctl, W, a.stats)) {
+                aborted = true;
+                break;
+            }
+            const uint32_t hi = ld_acq(&ctl->tail);
+            if (leader && tid == 0) {
+                ctl->cc = 0;                       // chunk counter of this level's expansion
+                ctl->maxsig[d & 1] = 0;            // filled while expanding level d
+                ctl->sdeg[(d + 1) & 1] = 0;        // filled by the next level's pass
+            }
             // fix the masks of the level-d entries and fold them into seen
             uint32_t sdeg = 0;
-            for (uint32_t i = lo + tid; i < hi; i += WG) {
+            for (uint32_t i = lo + gtid; i < hi; i += gthreads) {
                 const uint32_t w = lv[i];
                 const uint64_t m = nxt[w];
                 lm[i] = m;
@@ -303,26 +399,28 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 sdeg += a.row_ptr[w + 1] - a.row_ptr[w];
             }
             sdeg = wave_sum_u32(sdeg);
-            if (lane == 0 && sdeg) atomicAdd(&L.sdeg, sdeg);
-            if (tid == 0) {
+            if (lane == 0 && sdeg) atomicAdd(&ctl->sdeg[d & 1], sdeg);
+            if (leader && tid == 0) {
                 lvl[d] = lo;
                 lvl[d + 1] = hi;
             }
-            level_barrier();
+            if (!team_sync(L, ctl, W, a.stats)) {
+                aborted = true;
+                break;
+            }
             if (hi == lo) break;   // level d is empty: the sweep is over (levels 0..d-1)
             const uint64_t room = (uint64_t)a.cap - hi;
-            if (d + 2 > a.max_levels || room < min<uint64_t>(n, L.sdeg)) {
+            if (d + 2 > a.max_levels || room < min<uint64_t>(n, ld_acq(&ctl->sdeg[d & 1]))) {
                 stopped = true;
                 d += 1;
                 break;
             }
-            const uint64_t max_here = L.maxsig;   // largest count seen while expanding level d-1
-            if (d >= 1) max_prev = max_here;
-            const bool safe = d == 0 || (double)max_prev * a.in2 < kSafeSigma;
-            __syncthreads();
-            if (tid == 0) L.maxsig = 0;
-            __syncthreads();
-            for (uint32_t c0 = lo; c0 < hi; c0 += WG) {
+            // no carry is possible this level if (max count on level d-1) * maxin^2 < 2^64
+            const bool safe = d == 0 || (double)ld_acq(&ctl->maxsig[(d + 1) & 1]) * a.in2 < kSafeSigma;
+            for (;;) {
+                const uint32_t ch = claim_chunk(L, ctl);
+                const uint32_t c0 = lo + ch * WG;
+                if (c0 >= hi) break;
                 const uint32_t i = c0 + tid;
                 uint32_t v = 0, beg = 0, deg = 0;
                 uint64_t f = 0;
@@ -344,26 +442,43 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     const uint32_t j = find_owner<WG>(L.off, u);
                     const uint32_t e0 = L.eb[j] + (u - L.off[j]) * 64;
                     const uint32_t e1 = min(L.eb[j] + L.ed[j], e0 + 64);
-                    fwd_unit<WG>(a, L, seen, nxt, sig, lv, L.ev[j], L.em[j], e0, e1, safe);
+                    fwd_unit<WG>(a, L, ctl, seen, nxt, sig, lv, L.ev[j], L.em[j], e0, e1, safe);
                 }
                 __syncthreads();
+            }
+            if (tid == 0) {   // flush this workgroup's level results to the team
+                if (L.maxsig) atomicMax((unsigned long long*)&ctl->maxsig[d & 1], (unsigned long long)L.maxsig);
+                if (L.ovf) atomicOr((unsigned long long*)&ctl->ovf, (unsigned long long)L.ovf);
+                L.maxsig = 0;
+                L.ovf = 0;
             }
             lo = hi;
             ++d;
         }
+        if (aborted) break;
         const uint32_t nlev = d;            // levels 0..nlev-1 hold entries
-        const uint32_t n_entries = L.tail;
-        const uint64_t ovf = stopped ? lanes : (L.ovf & lanes);
+        const uint32_t n_entries = ld_acq(&ctl->tail);
+        const uint64_t ovf = stopped ? lanes : (ld_acq(&ctl->ovf) & lanes);
         // ---------------- backward sweep ----------------
         if (!stopped) {
-            if (tid == 0) lvl[nlev + 1] = lvl[nlev];
-            level_barrier();
-            for (int dd = (int)nlev - 1; dd >= 0; --dd) {
+            if (leader && tid == 0) lvl[nlev + 1] = lvl[nlev];
+            for (int dd = (int)nlev - 1; dd >= 0 && !aborted; --dd) {
+                if (!team_sync(L, ctl, W, a.stats)) {
+                    aborted = true;
+                    break;
+                }
                 const uint32_t lo_d = lvl[dd], hi_d = lvl[dd + 1];
                 const uint32_t lo_n = lvl[dd + 1], hi_n = lvl[dd + 2];
-                for (uint32_t i = lo_n + tid; i < hi_n; i += WG) nxt[lv[i]] = lm[i] & ~ovf;
-                level_barrier();
-                for (uint32_t c0 = lo_d; c0 < hi_d; c0 += WG) {
+                if (leader && tid == 0) ctl->cc = 0;
+                for (uint32_t i = lo_n + gtid; i < hi_n; i += gthreads) nxt[lv[i]] = lm[i] & ~ovf;
+                if (!team_sync(L, ctl, W, a.stats)) {
+                    aborted = true;
+                    break;
+                }
+                for (;;) {
+                    const uint32_t ch = claim_chunk(L, ctl);
+                    const uint32_t c0 = lo_d + ch * WG;
+                    if (c0 >= hi_d) break;
                     const uint32_t i = c0 + tid;
                     uint32_t v = 0, beg = 0, deg = 0, np = 0;
                     uint64_t f = 0;
@@ -388,7 +503,8 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     L.eb[tid] = beg;
                     L.ed[tid] = deg;
                     L.eh[tid] = row;
-                    level_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    __syncthreads();
                     for (uint32_t u = wave; u < units; u += NW) {
                         const uint32_t j = find_owner<WG>(L.off, u);
                         const uint32_t vj = L.ev[j];
@@ -435,7 +551,9 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                             unsafeAtomicAdd(&hacc[(size_t)hr * 64 + lane], acc);
                         }
                     }
-                    level_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    __syncthreads();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     const uint32_t nh = L.nhub;
                     for (uint32_t h = wave; h < nh; h += NW) {
                         const uint32_t j = L.hub_ent[h];
@@ -446,15 +564,19 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     if (tid == 0) L.nhub = 0;
                     __syncthreads();
                 }
-                for (uint32_t i = lo_n + tid; i < hi_n; i += WG) nxt[lv[i]] = 0ull;
-                level_barrier();
+                if (!team_sync(L, ctl, W, a.stats)) {
+                    aborted = true;
+                    break;
+                }
+                for (uint32_t i = lo_n + gtid; i < hi_n; i += gthreads) nxt[lv[i]] = 0ull;
             }
         }
+        if (aborted) break;
         // ---------------- reset the touched state ----------------
-        for (uint32_t i = wave; i < n_entries; i += NW) {
+        if (!team_sync(L, ctl, W, a.stats)) break;
+        for (uint32_t i = gwave; i < n_entries; i += gwaves) {
             const uint32_t v = lv[i];
-            uint64_t m = lm[i];
-            if (stopped && i >= lvl[nlev]) m = ~0ull;   // defensive: entries never finalised
+            const uint64_t m = lm[i];
             if ((m >> lane) & 1ull) sig[(size_t)v * 64 + lane] = 0ull;
             if (lane == 0) {
                 seen[v] = 0ull;
@@ -462,7 +584,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             }
         }
         // sources this kernel did not finish go to the per-source kernel
-        if (tid == 0) {
+        if (leader && tid == 0) {
             if (ovf) {
                 const uint32_t cnt = (uint32_t)__builtin_popcountll(ovf);
                 uint32_t pos = atomicAdd(a.retry_count, cnt);
@@ -476,7 +598,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             n_done += (uint32_t)__builtin_popcountll(lanes & ~ovf);
             if (!stopped) levels_max = max(levels_max, nlev);
         }
-        level_barrier();
+        if (!team_sync(L, ctl, W, a.stats)) break;
     }
     // counters of everything this workgroup finished
     const uint32_t r_w = wave_sum_u32(reached), g_w = wave_sum_u32(dagc), n_w = wave_sum_u32(entries);
@@ -577,8 +699,9 @@ int msb_occupancy(int wg) {
 
 // Device state of the batched path for one graph size, reused between calls.
 struct MsbPool {
-    int slots = 0;
+    int teams = 0, wgs = 0;
     uint32_t n = 0, cap = 0, max_levels = 0, hub_rows = 0;
+    TeamCtl* ctl = nullptr;
     uint64_t *seen = nullptr, *nxt = nullptr, *sig = nullptr, *lst_m = nullptr;
     double* hacc = nullptr;
     uint32_t *lst_v = nullptr, *lvl = nullptr;
@@ -588,13 +711,13 @@ struct MsbPool {
     uint32_t* small = nullptr;      // hist[33] cursor[33] plan_count retry_count
 };
 
-size_t msb_slot_bytes(uint32_t n, uint32_t cap, uint32_t max_levels, uint32_t hub_rows) {
-    return (size_t)n * (8 + 8 + 512) + (size_t)cap * 12 + 4 * ((size_t)max_levels + 2) + (size_t)hub_rows * 512;
+size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels) {
+    return sizeof(TeamCtl) + (size_t)n * (8 + 8 + 512) + (size_t)cap * 12 + 4 * ((size_t)max_levels + 2);
 }
 
 void msb_pool_free(MsbPool& p) {
-    for (void* q : {(void*)p.seen, (void*)p.nxt, (void*)p.sig, (void*)p.lst_m, (void*)p.hacc, (void*)p.lst_v,
-                    (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small})
+    for (void* q : {(void*)p.ctl, (void*)p.seen, (void*)p.nxt, (void*)p.sig, (void*)p.lst_m, (void*)p.hacc,
+                    (void*)p.lst_v, (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small})
         if (q) (void)hipFree(q);
     p = MsbPool{};
 }
@@ -606,64 +729,77 @@ void msb_pool_delete(MsbPool* p) {
         delete p;
     }
 }
+// A team that gave up on a barrier leaves its state dirty: drop the pool.
+void msb_pool_discard(MsbPool* p) {
+    if (p) msb_pool_free(*p);
+}
 
-static void msb_pool_ensure(MsbPool& p, uint32_t n, int slots, uint32_t cap, uint32_t max_levels, uint32_t hub_rows,
-                            uint32_t plan_cap, hipStream_t st) {
-    if (p.seen && p.n == n && p.slots >= slots && p.cap >= cap && p.max_levels >= max_levels &&
+static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t cap, uint32_t max_levels,
+                            uint32_t hub_rows, uint32_t plan_cap, hipStream_t st) {
+    if (p.seen && p.n == n && p.teams >= teams && p.wgs >= wgs && p.cap >= cap && p.max_levels >= max_levels &&
         p.hub_rows >= hub_rows && p.plan_cap >= plan_cap)
         return;
     BC_HIP_TRY(hipStreamSynchronize(st));
     msb_pool_free(p);
     p.n = n;
-    p.slots = slots;
+    p.teams = teams;
+    p.wgs = wgs;
     p.cap = cap;
     p.max_levels = max_levels;
     p.hub_rows = hub_rows;
     p.plan_cap = std::max<uint32_t>(plan_cap, 1);
-    BC_HIP_TRY(hipMalloc((void**)&p.seen, (size_t)slots * n * 8));
-    BC_HIP_TRY(hipMalloc((void**)&p.nxt, (size_t)slots * n * 8));
-    BC_HIP_TRY(hipMalloc((void**)&p.sig, (size_t)slots * n * 512));
-    BC_HIP_TRY(hipMalloc((void**)&p.hacc, (size_t)slots * hub_rows * 512));
-    BC_HIP_TRY(hipMalloc((void**)&p.lst_v, (size_t)slots * cap * 4));
-    BC_HIP_TRY(hipMalloc((void**)&p.lst_m, (size_t)slots * cap * 8));
-    BC_HIP_TRY(hipMalloc((void**)&p.lvl, (size_t)slots * (max_levels + 2) * 4));
+    BC_HIP_TRY(hipMalloc((void**)&p.ctl, (size_t)teams * sizeof(TeamCtl)));
+    BC_HIP_TRY(hipMalloc((void**)&p.seen, (size_t)teams * n * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.nxt, (size_t)teams * n * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.sig, (size_t)teams * n * 512));
+    BC_HIP_TRY(hipMalloc((void**)&p.hacc, (size_t)wgs * hub_rows * 512));
+    BC_HIP_TRY(hipMalloc((void**)&p.lst_v, (size_t)teams * cap * 4));
+    BC_HIP_TRY(hipMalloc((void**)&p.lst_m, (size_t)teams * cap * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.lvl, (size_t)teams * (max_levels + 2) * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.plan, (size_t)p.plan_cap * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.retry, (size_t)p.plan_cap * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.small, 128 * 4));
-    const size_t words = (size_t)slots * n;
+    const size_t words = (size_t)teams * n;
     const unsigned g1 = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.seen, words);
     hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.nxt, words);
     const unsigned g2 = (unsigned)std::min<size_t>((words * 64 + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u64, dim3(g2), dim3(256), 0, st, p.sig, words * 64);
+    const size_t cw = (size_t)teams * sizeof(TeamCtl) / 8;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::max<size_t>(1, std::min<size_t>((cw + 255) / 256, 1024))),
+                       dim3(256), 0, st, (uint64_t*)p.ctl, cw);
     BC_HIP_TRY(hipGetLastError());
 }
 
 // Enqueues the batched path: source plan, batched sweeps, then the per-source kernel on the
 // sources handed back.  `retry_launch` enqueues that per-source launch over (list, count).
 void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
-                     int wg, int slots_cap, hipStream_t st,
+                     int wg, int team_knob, int slots_cap, hipStream_t st,
                      void (*retry_launch)(void*, const uint32_t*, const uint32_t*, uint32_t, hipStream_t),
                      void* retry_ctx) {
     const DevInfo& di = dev_info(g.device);
     wg = msb_norm_wg(wg);
     const uint32_t n = (uint32_t)g.n;
     const uint32_t active_max = sources ? k : (uint32_t)(g.n - g.zero_out_degree);
-    const uint32_t batches = (active_max + 63) / 64;
+    const uint32_t batches = std::max<uint32_t>((active_max + 63) / 64, 1);
     int per_cu = msb_occupancy(wg);
     BC_REQUIRE(per_cu >= 1, BC_E_HIP, "batched kernel does not fit on a compute unit");
-    int slots = std::min<long>((long)per_cu * di.cus, std::max<uint32_t>(batches, 1));
-    if (slots_cap > 0) slots = std::min(slots, slots_cap);
+    const long max_wgs = (long)per_cu * di.cus;
+    // state slots: one per team; the kernel forms min(batches, slots) teams on the device
+    long teams = std::min<long>(batches, max_wgs);
+    if (team_knob > 0) teams = std::min<long>(teams, std::max<long>(1, max_wgs / team_knob));
+    if (slots_cap > 0) teams = std::min<long>(teams, slots_cap);
     const uint32_t cap = (uint32_t)std::min<uint64_t>((uint64_t)n * 8 + 64, 0xffffffffull);
     const uint32_t max_levels = 1024;
     // bound the pool by free device memory (keep half of it for everything else)
     size_t free_b = 0, total_b = 0;
     BC_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    const size_t per_slot = msb_slot_bytes(n, cap, max_levels, (uint32_t)wg);
-    const size_t have = (size_t)p.slots >= (size_t)slots && p.n == n ? (size_t)p.slots * per_slot : 0;
-    const size_t budget = (free_b + have) / 2;
-    slots = (int)std::max<size_t>(1, std::min<size_t>(slots, budget / std::max<size_t>(per_slot, 1)));
-    msb_pool_ensure(p, n, slots, cap, max_levels, (uint32_t)wg, std::max<uint32_t>(k, n), st);
+    const size_t per_team = msb_team_bytes(n, cap, max_levels);
+    const size_t have = p.n == n ? (size_t)p.teams * msb_team_bytes(n, p.cap, p.max_levels) : 0;
+    const size_t budget = (free_b + have) / 2 - std::min<size_t>((free_b + have) / 2, (size_t)max_wgs * wg * 512);
+    teams = (long)std::max<size_t>(1, std::min<size_t>(teams, budget / std::max<size_t>(per_team, 1)));
+    const int grid = (int)max_wgs;
+    msb_pool_ensure(p, n, (int)teams, grid, cap, max_levels, (uint32_t)wg, std::max<uint32_t>(k, n), st);
 
     uint32_t* hist = p.small;
     uint32_t* cursor = p.small + 40;
@@ -686,6 +822,7 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.retry = p.retry;
     a.retry_count = retry_count;
     a.stats = stats;
+    a.ctl = p.ctl;
     a.seen = p.seen;
     a.nxt = p.nxt;
     a.sig = p.sig;
@@ -697,13 +834,18 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.cap = p.cap;
     a.max_levels = p.max_levels;
     a.hub_rows = p.hub_rows;
+    a.team_size = team_knob > 0 ? (uint32_t)team_knob : 0u;
+    a.pool_teams = (uint32_t)p.teams;
     a.in2 = (double)g.max_in_degree * (double)g.max_in_degree;
-    switch (wg) {
-        case 256: hipLaunchKernelGGL(k_msb<256>, dim3(slots), dim3(256), 0, st, a); break;
-        case 512: hipLaunchKernelGGL(k_msb<512>, dim3(slots), dim3(512), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_msb<1024>, dim3(slots), dim3(1024), 0, st, a); break;
+    void* args[] = {&a};
+    // members of a team wait for each other at level boundaries: a cooperative launch
+    // guarantees that every workgroup of the grid is resident at once
+    hipError_t e = hipLaunchCooperativeKernel(msb_fn(wg), dim3(grid), dim3(wg), args, 0, st);
+    if (e == hipErrorCooperativeLaunchTooLarge) {   // the runtime's residency bound is tighter
+        (void)hipGetLastError();
+        e = hipLaunchCooperativeKernel(msb_fn(wg), dim3(std::max(1, grid / 2)), dim3(wg), args, 0, st);
     }
-    BC_HIP_TRY(hipGetLastError());
+    BC_HIP_TRY(e);
     retry_launch(retry_ctx, p.retry, retry_count, std::max<uint32_t>(k, n), st);
 }
 

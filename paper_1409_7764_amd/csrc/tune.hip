@@ -24,7 +24,7 @@ bool tuning_enabled() {
 Knobs default_knobs(const Graph& g) {
     Knobs k;
     k.wg_size = 256;
-    k.team = 1;
+    k.team = 0;     // batched path: workgroups per batch chosen from the batch count
     k.teams = 0;
     k.hub = 64;
     k.lds_max_n = 4096;
@@ -61,9 +61,9 @@ void load_cache_locked() {
     char key[256];
     Knobs k;
     int ug = 0;
-    // one entry per line: key wg hub lds_max_n batched batch_wg teams use_graph
-    while (std::fscanf(f, "%255s %d %d %d %d %d %d %d", key, &k.wg_size, &k.hub, &k.lds_max_n, &k.batched,
-                       &k.batch_wg, &k.teams, &ug) == 8) {
+    // one entry per line: key wg hub lds_max_n batched batch_wg teams use_graph team
+    while (std::fscanf(f, "%255s %d %d %d %d %d %d %d %d", key, &k.wg_size, &k.hub, &k.lds_max_n, &k.batched,
+                       &k.batch_wg, &k.teams, &ug, &k.team) == 9) {
         k.use_graph = ug != 0;
         g_cache[key] = k;
     }
@@ -77,8 +77,8 @@ void save_cache_locked() {
     if (!f) return;
     for (const auto& kv : g_cache) {
         const Knobs& k = kv.second;
-        std::fprintf(f, "%s %d %d %d %d %d %d %d\n", kv.first.c_str(), k.wg_size, k.hub, k.lds_max_n, k.batched,
-                     k.batch_wg, k.teams, k.use_graph ? 1 : 0);
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", kv.first.c_str(), k.wg_size, k.hub, k.lds_max_n,
+                     k.batched, k.batch_wg, k.teams, k.use_graph ? 1 : 0, k.team);
     }
     std::fclose(f);
 }
@@ -105,8 +105,8 @@ Knobs resolve_knobs(Graph& g, const bc_tuning* t) {
         k.wg_size = t->wg_size;
     }
     if (t->wgs_per_source) {
-        BC_REQUIRE(t->wgs_per_source == 1, BC_E_INVAL, "wgs_per_source must be 1");
-        k.team = 1;
+        BC_REQUIRE(t->wgs_per_source >= 1 && t->wgs_per_source <= 64, BC_E_INVAL, "wgs_per_source must be in [1, 64]");
+        k.team = t->wgs_per_source;
     }
     if (t->sources_per_launch) {
         BC_REQUIRE(t->sources_per_launch > 0, BC_E_INVAL, "sources_per_launch must be > 0");

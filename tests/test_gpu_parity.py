@@ -166,6 +166,26 @@ def test_batched_exact(bc, bwg, case):
     g.free()
 
 
+@pytest.mark.parametrize("team", [1, 2, 4, 8, 32])
+def test_batched_teams(bc, team):
+    """Several workgroups per batch (level barriers across workgroups)."""
+    n, u, v = gg.rmat(12, 16, 6)
+    want, ovf, st = oracle_exact("rmat12_16_6", n, u, v)
+    say("batched team", team)
+    g = bc.bc_build_csr(n, u, v)
+    got, info = bc.bc_exact(g, tuning=force(bc, "batched", wgs_per_source=team), info=True)
+    assert info["path"] == 2 and info["n_sources"] == n
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    rel_close(np_of(got), want, what=f"team={team}")
+    # few batches: the device picks the team size
+    S = gg.uniform_sources(n, 100, 3)
+    got, info = bc.bc_sampled(g, S, tuning=force(bc, "batched"), info=True)
+    want_s, _, st_s = oracle.bc(oracle.Graph(n, u, v), S)
+    assert info["reached"] == int(st_s[:, 0].sum())
+    rel_close(np_of(got), want_s, what="auto team")
+    g.free()
+
+
 def test_batched_sampled_multiset(bc):
     n, u, v = gg.rmat(12, 8, 9)
     g = bc.bc_build_csr(n, u, v)
