@@ -23,6 +23,10 @@ Graph::~Graph() {
     if (col) (void)hipFree(col);
     if (csc_ptr) (void)hipFree(csc_ptr);
     if (csc_row) (void)hipFree(csc_row);
+    if (perm) (void)hipFree(perm);
+    if (iperm) (void)hipFree(iperm);
+    if (prow) (void)hipFree(prow);
+    if (pcol) (void)hipFree(pcol);
     if (stats) (void)hipFree(stats);
     (void)hipSetDevice(prev);
 }

@@ -90,6 +90,14 @@ struct Graph {
     uint32_t* col = nullptr;       // m
     uint32_t* csc_ptr = nullptr;   // n+1
     uint32_t* csc_row = nullptr;   // m
+    // the kernels run on a copy with vertices relabelled by decreasing in-degree (graphs of
+    // at least kRelabelMinN vertices): the most often gathered targets then share cache lines
+    uint32_t* perm = nullptr;      // caller id -> kernel id (null: identity)
+    uint32_t* iperm = nullptr;     // kernel id -> caller id
+    uint32_t* prow = nullptr;      // kernel CSR (n+1), successors sorted per row
+    uint32_t* pcol = nullptr;      // m
+    const uint32_t* krow() const { return prow ? prow : row_ptr; }
+    const uint32_t* kcol() const { return pcol ? pcol : col; }
     uint32_t max_out_degree = 0;
     uint32_t max_in_degree = 0;
     uint32_t zero_out_degree = 0;  // vertices with no out-edges (sources that reach nothing)
@@ -109,6 +117,8 @@ struct DevInfo {
     std::string name;
 };
 const DevInfo& dev_info(int device);
+
+constexpr int32_t kRelabelMinN = 16384;
 
 // ---- CSR builder (csr_build.hip) --------------------------------------------------------
 void build_csr_device(int32_t n, int64_t m_in, const uint32_t* d_src, const uint32_t* d_dst,
@@ -137,7 +147,9 @@ struct WorkDesc {
     const uint32_t* row_ptr;
     const uint32_t* col;
     double* bc;
-    const uint32_t* sources;   // nullable: local item i is source src_base + i
+    const uint32_t* sources;   // nullable: local item i is source src_base + i (kernel ids)
+    const uint32_t* perm;      // nullable: caller id -> kernel id, applied to `sources`
+    const uint32_t* iperm;     // nullable: kernel id -> caller id, applied to every output index
     uint32_t* counters;        // nullable: per-descriptor {done, overflowed, levels_max, bad}
     int32_t n;
     uint32_t item_begin;       // first work item of this descriptor in the launch

@@ -350,7 +350,8 @@ __device__ void expand_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__
 template <bool F64, int WG, class S>
 __device__ void accumulate_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__ row_ptr,
                                  const uint32_t* __restrict__ col, uint32_t lo, uint32_t hi, int d, uint32_t hub,
-                                 uint32_t tpv_max, uint32_t src, double* __restrict__ bc, double* ex_delta) {
+                                 uint32_t tpv_max, uint32_t src, double* __restrict__ bc, double* ex_delta,
+                                 const uint32_t* __restrict__ iperm) {
     const unsigned tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
     constexpr unsigned NW = WG / 64;
     const int d1 = d + 1;
@@ -404,8 +405,9 @@ __device__ void accumulate_level(S& st, Scratch<WG>& L, const uint32_t* __restri
             const double sigma = F64 ? u2d(sv) : (double)sv;
             const double delta = sigma * own;
             st.set_val(v, d2u((1.0 + delta) / sigma));
-            if (v != src && delta != 0.0) unsafeAtomicAdd(&bc[v], delta);
-            if (ex_delta) ex_delta[v] = delta;
+            const uint32_t out = iperm ? iperm[v] : v;
+            if (v != src && delta != 0.0) unsafeAtomicAdd(&bc[out], delta);
+            if (ex_delta) ex_delta[out] = delta;
         }
         __syncthreads();
     }
@@ -462,16 +464,21 @@ __device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s,
         for (uint32_t i = tid; i < count; i += WG) {
             const uint32_t v = st.q(i);
             const uint64_t x = st.val(v);
-            if (a.ex_dist) a.ex_dist[v] = st.dist(v);
-            if (a.ex_sigma) a.ex_sigma[v] = f64 ? 0ull : x;
-            if (a.ex_sigma_f) a.ex_sigma_f[v] = f64 ? u2d(x) : (double)x;
+            const uint32_t out = D.iperm ? D.iperm[v] : v;
+            if (a.ex_dist) a.ex_dist[out] = st.dist(v);
+            if (a.ex_sigma) a.ex_sigma[out] = f64 ? 0ull : x;
+            if (a.ex_sigma_f) a.ex_sigma_f[out] = f64 ? u2d(x) : (double)x;
         }
     }
     uint32_t hi = count;
     for (int dd = nlev - 1; dd >= 0; --dd) {
         const uint32_t lo = st.level_begin(dd, hi);
-        if (f64) accumulate_level<true, WG>(st, L, D.row_ptr, D.col, lo, hi, dd, a.hub, a.tpv_max, s, D.bc, a.ex_delta);
-        else accumulate_level<false, WG>(st, L, D.row_ptr, D.col, lo, hi, dd, a.hub, a.tpv_max, s, D.bc, a.ex_delta);
+        if (f64)
+            accumulate_level<true, WG>(st, L, D.row_ptr, D.col, lo, hi, dd, a.hub, a.tpv_max, s, D.bc, a.ex_delta,
+                                       D.iperm);
+        else
+            accumulate_level<false, WG>(st, L, D.row_ptr, D.col, lo, hi, dd, a.hub, a.tpv_max, s, D.bc, a.ex_delta,
+                                        D.iperm);
         st.barrier();
         hi = lo;
     }
@@ -537,7 +544,10 @@ __device__ __forceinline__ bool claim_item(const LaunchArgs& a, Scratch<WG>& L, 
         const WorkDesc& D = a.descs[di];
         const uint32_t local = item - D.item_begin;
         s = D.sources ? D.sources[local] : D.src_base + local;
-        if (s < (uint32_t)D.n && (uint32_t)D.n <= n_cap) return true;
+        if (s < (uint32_t)D.n && (uint32_t)D.n <= n_cap) {
+            if (D.sources && D.perm) s = D.perm[s];   // caller id -> kernel id
+            return true;
+        }
         if (threadIdx.x == 0) {
             atomicAdd(&a.stats->bad_source, 1u);
             if (D.counters) {
@@ -803,7 +813,7 @@ MsbPool* msb_pool_new();
 void msb_pool_delete(MsbPool* p);
 void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
                      int wg, int team_knob, int slots_cap, hipStream_t st,
-                     void (*retry_launch)(void*, const uint32_t*, const uint32_t*, uint32_t, hipStream_t),
+                     void (*retry_launch)(void*, const uint32_t*, const uint32_t*, uint32_t, bool, hipStream_t),
                      void* retry_ctx);
 
 // Per-source launch over a device-resident list whose length is known only on the device
@@ -815,7 +825,9 @@ struct RetryCtx {
     double* bc;
 };
 
-static void retry_launch(void* ctx, const uint32_t* list, const uint32_t* count, uint32_t cap, hipStream_t st) {
+// `kernel_ids`: the list holds ids of the relabelled copy (else caller ids)
+static void retry_launch(void* ctx, const uint32_t* list, const uint32_t* count, uint32_t cap, bool kernel_ids,
+                         hipStream_t st) {
     RetryCtx& c = *reinterpret_cast<RetryCtx*>(ctx);
     Graph& g = *c.g;
     Knobs k = c.k;
@@ -828,10 +840,12 @@ static void retry_launch(void* ctx, const uint32_t* list, const uint32_t* count,
     p.args.lvl = c.gs->pool.lvl;
     p.args.slot_n = c.gs->pool.slot_n;
     WorkDesc d{};
-    d.row_ptr = g.row_ptr;
-    d.col = g.col;
+    d.row_ptr = g.krow();
+    d.col = g.kcol();
     d.bc = c.bc;
     d.sources = list;
+    d.perm = kernel_ids ? nullptr : g.perm;
+    d.iperm = g.iperm;
     d.n = g.n;
     d.num_items = cap;
     BC_HIP_TRY(hipMemcpyAsync(c.gs->rdesc, &d, sizeof(d), hipMemcpyHostToDevice, st));
@@ -867,10 +881,12 @@ int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
     if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
     WorkDesc d{};
-    d.row_ptr = g.row_ptr;
-    d.col = g.col;
+    d.row_ptr = g.krow();
+    d.col = g.kcol();
     d.bc = ra.bc;
     d.sources = ra.sources;
+    d.perm = g.perm;
+    d.iperm = g.iperm;
     d.counters = nullptr;
     d.n = g.n;
     d.item_begin = 0;
@@ -904,9 +920,11 @@ int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
     if (!gs.msb) gs.msb = msb_pool_new();
     WorkDesc d{};
-    d.row_ptr = g.row_ptr;
-    d.col = g.col;
+    d.row_ptr = g.krow();
+    d.col = g.kcol();
     d.bc = ra.bc;
+    d.perm = g.perm;
+    d.iperm = g.iperm;
     d.n = g.n;
     d.num_items = ra.num_items;
     BC_HIP_TRY(hipMemcpyAsync(gs.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
@@ -1026,8 +1044,10 @@ static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* b
                 const Graph* g = bp->graphs[gi];
                 WorkDesc& d = h[pos];
                 d = WorkDesc{};
-                d.row_ptr = g->row_ptr;
-                d.col = g->col;
+                d.row_ptr = g->krow();
+                d.col = g->kcol();
+                d.perm = g->perm;
+                d.iperm = g->iperm;
                 d.bc = bp->outs[gi];
                 d.sources = nullptr;
                 d.counters = bp->d_counters + 4 * pos;

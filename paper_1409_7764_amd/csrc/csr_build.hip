@@ -11,6 +11,7 @@
 #include "bc_internal.h"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace bcmi {
 namespace {
@@ -239,6 +240,37 @@ __global__ void k_max_u32(const uint32_t* x, uint64_t N, uint32_t* out) {
     if (lane_id() == 0) atomicMax(out, best);
 }
 
+// --- 6. relabelling by decreasing in-degree ------------------------------------------------
+__global__ void k_degree_keys(const uint32_t* csc_ptr, uint32_t n, uint32_t maxin, int vbits, uint64_t* keys) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        keys[v] = ((uint64_t)(maxin - (csc_ptr[v + 1] - csc_ptr[v])) << vbits) | v;
+}
+
+__global__ void k_perm_from_sorted(const uint64_t* keys, uint32_t n, int vbits, uint32_t* iperm, uint32_t* perm) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)(keys[i] & ((1ull << vbits) - 1));
+        iperm[i] = v;
+        perm[v] = i;
+    }
+}
+
+// relabelled edge keys, one thread per row
+__global__ void k_relabel_keys(const uint32_t* row_ptr, const uint32_t* col, uint32_t n, const uint32_t* perm,
+                               int vbits, uint64_t* keys) {
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        const uint64_t hi = (uint64_t)perm[u] << vbits;
+        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) keys[e] = hi | perm[col[e]];
+    }
+}
+
+__global__ void k_csr_from_sorted(const uint64_t* keys, uint64_t m, int vbits, uint32_t* col, uint32_t* deg) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[i];
+        col[i] = (uint32_t)(k & ((1ull << vbits) - 1));
+        atomicAdd(&deg[(uint32_t)(k >> vbits)], 1u);
+    }
+}
+
 // vertices with no out-edges (row_ptr still holds out-degrees)
 __global__ void k_count_zero(const uint32_t* deg, uint64_t N, uint32_t* out) {
     uint32_t c = 0;
@@ -337,6 +369,38 @@ void build_csr_device(int32_t n, int64_t m_in, const uint32_t* d_src, const uint
         h[2] = 0;
         BC_HIP_TRY(hipMalloc((void**)&g.col, sizeof(uint32_t)));
         BC_HIP_TRY(hipMalloc((void**)&g.csc_row, sizeof(uint32_t)));
+    }
+    const char* rl = std::getenv("BCMI_RELABEL");
+    if (m > 0 && n >= kRelabelMinN && !(rl && rl[0] == '0')) {
+        // kernel copy of the graph, vertices renumbered by decreasing in-degree (ties by id)
+        BC_HIP_TRY(hipStreamSynchronize(st));
+        const uint32_t maxin = h[2];
+        int dbits = 1;
+        while (dbits < 32 && (1ull << dbits) <= maxin) ++dbits;
+        uint64_t *dk = nullptr, *dt = nullptr;
+        BC_HIP_TRY(hipMallocAsync((void**)&dk, (size_t)n * 8, st));
+        BC_HIP_TRY(hipMallocAsync((void**)&dt, (size_t)n * 8, st));
+        BC_HIP_TRY(hipMalloc((void**)&g.perm, sizeof(uint32_t) * n));
+        BC_HIP_TRY(hipMalloc((void**)&g.iperm, sizeof(uint32_t) * n));
+        BC_HIP_TRY(hipMalloc((void**)&g.prow, sizeof(uint32_t) * (n + 1)));
+        BC_HIP_TRY(hipMalloc((void**)&g.pcol, sizeof(uint32_t) * m));
+        const unsigned gn = std::min<unsigned>(grid_for(n, 256), 4096);
+        hipLaunchKernelGGL(k_degree_keys, dim3(gn), dim3(256), 0, st, g.csc_ptr, (uint32_t)n, maxin, vbits, dk);
+        BC_HIP_TRY(hipGetLastError());
+        uint64_t* ds = radix_sort(dk, dt, (uint64_t)n, dbits + vbits, st);
+        hipLaunchKernelGGL(k_perm_from_sorted, dim3(gn), dim3(256), 0, st, ds, (uint32_t)n, vbits, g.iperm, g.perm);
+        BC_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_relabel_keys, dim3(gn), dim3(256), 0, st, g.row_ptr, g.col, (uint32_t)n, g.perm, vbits,
+                           keys);
+        BC_HIP_TRY(hipGetLastError());
+        uint64_t* rs = radix_sort(keys, tmp, m, 2 * vbits, st);
+        BC_HIP_TRY(hipMemsetAsync(g.prow, 0, sizeof(uint32_t) * (n + 1), st));
+        hipLaunchKernelGGL(k_csr_from_sorted, dim3(std::min<unsigned>(grid_for(m, 256), 8192)), dim3(256), 0, st, rs,
+                           (uint64_t)m, vbits, g.pcol, g.prow);
+        BC_HIP_TRY(hipGetLastError());
+        scan_u32(g.prow, g.prow, (uint64_t)n + 1, st);
+        BC_HIP_TRY(hipFreeAsync(dk, st));
+        BC_HIP_TRY(hipFreeAsync(dt, st));
     }
     if (keys) BC_HIP_TRY(hipFreeAsync(keys, st));
     if (tmp) BC_HIP_TRY(hipFreeAsync(tmp, st));

@@ -31,6 +31,7 @@
 #include "bc_internal.h"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace bcmi {
 
@@ -49,9 +50,10 @@ struct alignas(128) TeamCtl {
 };
 
 struct MsbArgs {
-    const uint32_t* row_ptr;
+    const uint32_t* row_ptr;     // kernel CSR
     const uint32_t* col;
-    double* bc;
+    double* bc;                  // caller's output, indexed through iperm
+    const uint32_t* iperm;       // nullable: kernel id -> caller id
     const uint32_t* plan;        // planned sources, batched in order
     const uint32_t* plan_count;  // [0]: number of planned sources
     uint32_t* retry;             // sources handed to the per-source kernel
@@ -66,6 +68,8 @@ struct MsbArgs {
     uint64_t* lst_m;             // [teams][cap]
     uint32_t* lvl;               // [teams][max_levels + 2]
     int32_t n;
+    uint64_t mask_stride;        // elements between two teams' seen / nxt arrays
+    uint64_t sig_stride;         // elements between two teams' count rows
     uint32_t cap;
     uint32_t max_levels;
     uint32_t hub_rows;
@@ -232,7 +236,10 @@ __device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, TeamCt
     bool fresh = false;
     if (ok) {
         dag = f & ~seen[w];
-        if (dag) fresh = atomicOr((unsigned long long*)&nxt[w], (unsigned long long)dag) == 0ull;
+        // bits only get set during a level, so a plain read that already shows every bit of
+        // dag (stale reads show fewer) proves the atomic would change nothing and that this
+        // edge is not the vertex's first discovery: skip it (hot vertices get many such edges)
+        if (dag && (dag & ~nxt[w])) fresh = atomicOr((unsigned long long*)&nxt[w], (unsigned long long)dag) == 0ull;
     }
     const uint64_t mx = wave_max64(sv);
     if (lane == 0 && mx > L.maxsig) atomicMax((unsigned long long*)&L.maxsig, (unsigned long long)mx);
@@ -283,7 +290,7 @@ __device__ __forceinline__ void finish_entry(const MsbArgs& a, uint64_t* sig, ui
     }
     c = wave_sum(c);
     if (lane == 0) {
-        if (c != 0.0) unsafeAtomicAdd(&a.bc[v], c);
+        if (c != 0.0) unsafeAtomicAdd(&a.bc[a.iperm ? a.iperm[v] : v], c);
         const uint32_t pc = (uint32_t)__builtin_popcountll(f);
         reached += pc;
         examined += (uint64_t)pc * deg;
@@ -331,9 +338,9 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     const bool leader = member == 0;
     TeamCtl* ctl = a.ctl + team;
     const size_t n = (size_t)a.n;
-    uint64_t* seen = a.seen + (size_t)team * n;
-    uint64_t* nxt = a.nxt + (size_t)team * n;
-    uint64_t* sig = a.sig + (size_t)team * n * 64;
+    uint64_t* seen = a.seen + (size_t)team * a.mask_stride;
+    uint64_t* nxt = a.nxt + (size_t)team * a.mask_stride;
+    uint64_t* sig = a.sig + (size_t)team * a.sig_stride;
     double* hacc = a.hacc + (size_t)blockIdx.x * a.hub_rows * 64;
     uint32_t* lv = a.lst_v + (size_t)team * a.cap;
     uint64_t* lm = a.lst_m + (size_t)team * a.cap;
@@ -624,18 +631,19 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
 // ---- source plan: valid sources with out-edges, grouped by out-degree (largest first) ----
 constexpr int kPlanBuckets = 33;   // bucket q = count of leading zeros of the out-degree; 32 = no out-edges
 
-__global__ void k_plan_hist(const uint32_t* row_ptr, const uint32_t* srcs, uint32_t k, uint32_t n, uint32_t* hist,
-                            CallStats* stats) {
+__global__ void k_plan_hist(const uint32_t* row_ptr, const uint32_t* srcs, const uint32_t* perm, uint32_t k,
+                            uint32_t n, uint32_t* hist, CallStats* stats) {
     __shared__ uint32_t h[kPlanBuckets];
     if (threadIdx.x < kPlanBuckets) h[threadIdx.x] = 0;
     __syncthreads();
     uint32_t bad = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-        const uint32_t s = srcs ? srcs[i] : i;
+        uint32_t s = srcs ? srcs[i] : i;
         if (s >= n) {
             ++bad;
             continue;
         }
+        if (srcs && perm) s = perm[s];
         const uint32_t deg = row_ptr[s + 1] - row_ptr[s];
         atomicAdd(&h[deg ? __clz(deg) : 32], 1u);
     }
@@ -659,11 +667,12 @@ __global__ void k_plan_scan(const uint32_t* hist, uint32_t* cursor, uint32_t* pl
     if (idle && stats->levels_max < 1) stats->levels_max = 1;
 }
 
-__global__ void k_plan_scatter(const uint32_t* row_ptr, const uint32_t* srcs, uint32_t k, uint32_t n,
-                               uint32_t* cursor, uint32_t* plan) {
+__global__ void k_plan_scatter(const uint32_t* row_ptr, const uint32_t* srcs, const uint32_t* perm, uint32_t k,
+                               uint32_t n, uint32_t* cursor, uint32_t* plan) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-        const uint32_t s = srcs ? srcs[i] : i;
+        uint32_t s = srcs ? srcs[i] : i;
         if (s >= n) continue;
+        if (srcs && perm) s = perm[s];
         const uint32_t deg = row_ptr[s + 1] - row_ptr[s];
         if (!deg) continue;
         plan[atomicAdd(&cursor[__clz(deg)], 1u)] = s;
@@ -698,9 +707,14 @@ int msb_occupancy(int wg) {
 }
 
 // Device state of the batched path for one graph size, reused between calls.
+// Team arrays are staggered by an odd number of 4 KiB pages so that the same vertex of
+// different teams does not map to the same memory channel.
+constexpr uint64_t kStaggerWords = 37 * 512;
+
 struct MsbPool {
     int teams = 0, wgs = 0;
     uint32_t n = 0, cap = 0, max_levels = 0, hub_rows = 0;
+    uint64_t mask_stride = 0, sig_stride = 0;
     TeamCtl* ctl = nullptr;
     uint64_t *seen = nullptr, *nxt = nullptr, *sig = nullptr, *lst_m = nullptr;
     double* hacc = nullptr;
@@ -712,7 +726,8 @@ struct MsbPool {
 };
 
 size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels) {
-    return sizeof(TeamCtl) + (size_t)n * (8 + 8 + 512) + (size_t)cap * 12 + 4 * ((size_t)max_levels + 2);
+    return sizeof(TeamCtl) + (size_t)n * (8 + 8 + 512) + 3 * kStaggerWords * 8 + (size_t)cap * 12 +
+           4 * ((size_t)max_levels + 2);
 }
 
 void msb_pool_free(MsbPool& p) {
@@ -748,10 +763,12 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     p.max_levels = max_levels;
     p.hub_rows = hub_rows;
     p.plan_cap = std::max<uint32_t>(plan_cap, 1);
+    p.mask_stride = (uint64_t)n + kStaggerWords / 8;
+    p.sig_stride = (uint64_t)n * 64 + kStaggerWords;
     BC_HIP_TRY(hipMalloc((void**)&p.ctl, (size_t)teams * sizeof(TeamCtl)));
-    BC_HIP_TRY(hipMalloc((void**)&p.seen, (size_t)teams * n * 8));
-    BC_HIP_TRY(hipMalloc((void**)&p.nxt, (size_t)teams * n * 8));
-    BC_HIP_TRY(hipMalloc((void**)&p.sig, (size_t)teams * n * 512));
+    BC_HIP_TRY(hipMalloc((void**)&p.seen, (size_t)teams * p.mask_stride * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.nxt, (size_t)teams * p.mask_stride * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.sig, (size_t)teams * p.sig_stride * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.hacc, (size_t)wgs * hub_rows * 512));
     BC_HIP_TRY(hipMalloc((void**)&p.lst_v, (size_t)teams * cap * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.lst_m, (size_t)teams * cap * 8));
@@ -759,12 +776,13 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     BC_HIP_TRY(hipMalloc((void**)&p.plan, (size_t)p.plan_cap * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.retry, (size_t)p.plan_cap * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.small, 128 * 4));
-    const size_t words = (size_t)teams * n;
+    const size_t words = (size_t)teams * p.mask_stride;
     const unsigned g1 = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.seen, words);
     hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.nxt, words);
-    const unsigned g2 = (unsigned)std::min<size_t>((words * 64 + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_zero_u64, dim3(g2), dim3(256), 0, st, p.sig, words * 64);
+    const size_t swords = (size_t)teams * p.sig_stride;
+    const unsigned g2 = (unsigned)std::min<size_t>((swords + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero_u64, dim3(g2), dim3(256), 0, st, p.sig, swords);
     const size_t cw = (size_t)teams * sizeof(TeamCtl) / 8;
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::max<size_t>(1, std::min<size_t>((cw + 255) / 256, 1024))),
                        dim3(256), 0, st, (uint64_t*)p.ctl, cw);
@@ -775,7 +793,7 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
 // sources handed back.  `retry_launch` enqueues that per-source launch over (list, count).
 void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
                      int wg, int team_knob, int slots_cap, hipStream_t st,
-                     void (*retry_launch)(void*, const uint32_t*, const uint32_t*, uint32_t, hipStream_t),
+                     void (*retry_launch)(void*, const uint32_t*, const uint32_t*, uint32_t, bool, hipStream_t),
                      void* retry_ctx) {
     const DevInfo& di = dev_info(g.device);
     wg = msb_norm_wg(wg);
@@ -808,15 +826,22 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, st, p.small, 128u);
     const uint32_t items = sources ? k : n;
     const unsigned gp = std::max(1u, std::min<unsigned>((items + 255) / 256, 2048));
-    hipLaunchKernelGGL(k_plan_hist, dim3(gp), dim3(256), 0, st, g.row_ptr, sources, items, n, hist, stats);
+    // the batched kernel runs on the caller's numbering unless BCMI_MSB_RELABEL=1
+    const char* mr = std::getenv("BCMI_MSB_RELABEL");
+    const bool rel = mr && mr[0] == '1' && g.perm;
+    const uint32_t* krow = rel ? g.prow : g.row_ptr;
+    const uint32_t* kcol = rel ? g.pcol : g.col;
+    const uint32_t* kperm = rel ? g.perm : nullptr;
+    hipLaunchKernelGGL(k_plan_hist, dim3(gp), dim3(256), 0, st, krow, sources, kperm, items, n, hist, stats);
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, st, hist, cursor, plan_count, stats);
-    hipLaunchKernelGGL(k_plan_scatter, dim3(gp), dim3(256), 0, st, g.row_ptr, sources, items, n, cursor, p.plan);
+    hipLaunchKernelGGL(k_plan_scatter, dim3(gp), dim3(256), 0, st, krow, sources, kperm, items, n, cursor, p.plan);
     BC_HIP_TRY(hipGetLastError());
 
     MsbArgs a{};
-    a.row_ptr = g.row_ptr;
-    a.col = g.col;
+    a.row_ptr = krow;
+    a.col = kcol;
     a.bc = bc;
+    a.iperm = rel ? g.iperm : nullptr;
     a.plan = p.plan;
     a.plan_count = plan_count;
     a.retry = p.retry;
@@ -831,6 +856,8 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.lst_m = p.lst_m;
     a.lvl = p.lvl;
     a.n = g.n;
+    a.mask_stride = p.mask_stride;
+    a.sig_stride = p.sig_stride;
     a.cap = p.cap;
     a.max_levels = p.max_levels;
     a.hub_rows = p.hub_rows;
@@ -846,7 +873,7 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
         e = hipLaunchCooperativeKernel(msb_fn(wg), dim3(std::max(1, grid / 2)), dim3(wg), args, 0, st);
     }
     BC_HIP_TRY(e);
-    retry_launch(retry_ctx, p.retry, retry_count, std::max<uint32_t>(k, n), st);
+    retry_launch(retry_ctx, p.retry, retry_count, std::max<uint32_t>(k, n), rel, st);
 }
 
 }  // namespace bcmi

@@ -166,8 +166,10 @@ struct Server {
                 if (items[c] >= item_cap[c]) continue;
                 const uint32_t take = std::min(r.k - r.next, r.lds ? kChunkLds : kChunkGlobal);
                 WorkDesc d{};
-                d.row_ptr = r.g->row_ptr;
-                d.col = r.g->col;
+                d.row_ptr = r.g->krow();
+                d.col = r.g->kcol();
+                d.perm = r.g->perm;
+                d.iperm = r.g->iperm;
                 d.bc = r.d_bc;
                 d.sources = r.exact ? nullptr : r.d_sources + r.next;
                 d.src_base = r.exact ? r.next : 0u;

@@ -186,6 +186,32 @@ def test_batched_teams(bc, team):
     g.free()
 
 
+def test_relabelled_graph_every_path(bc):
+    """Graphs from 16,384 vertices run on an internally renumbered copy; every output must
+    still come back in the caller's vertex ids."""
+    n, u, v = gg.rmat(14, 8, 21)
+    g = bc.bc_build_csr(n, u, v)
+    o = oracle.Graph(n, u, v)
+    rp, col, _, _ = g.arrays()
+    assert np.array_equal(col.numpy(), o.col.astype(np.int64))     # caller's ids, untouched
+    outdeg = np.diff(o.row_ptr.astype(np.int64))
+    for s in [int(np.argmax(outdeg)), 5, n - 3]:
+        r = bc.bc_sssp(g, s)
+        w = oracle.brandes_source(o, s)
+        assert np.array_equal(np_of(r["dist"]), w["dist"])
+        assert np.array_equal(np_of(r["sigma_u64"]).view(np.uint64), w["sigma"])
+        rel_close(np_of(r["delta"]), w["delta"], what="delta")
+    S = np.concatenate([gg.uniform_sources(n, 200, 22), np.array([int(np.argmax(outdeg))] * 2, np.uint32)])
+    want, _, st = oracle.bc(o, S)
+    for path in ["global", "batched"]:
+        say("relabelled", path)
+        got, info = bc.bc_sampled(g, S, tuning=force(bc, path), info=True)
+        assert info["path"] == PATH_CODE[path]
+        assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+        rel_close(np_of(got), want, what=path)
+    g.free()
+
+
 def test_batched_sampled_multiset(bc):
     n, u, v = gg.rmat(12, 8, 9)
     g = bc.bc_build_csr(n, u, v)
