@@ -188,6 +188,7 @@ def bench_single(args, torch, bcmi, gg):
             "sigma_fp64_fallback_sources": inf["n_sigma_fp64_fallback"],
             "path": ["global", "lds", "batched"][inf["path"]], "tuning": tune,
             "batch_entries": inf["batch_entries"], "batch_edge_visits": inf["batch_edge_visits"],
+            "batch_cycles_fwd_bwd_reset": inf["batch_cycles"],
             "kernel_ms_all": [i["kernel_ms"] for i in infos],
         },
     }

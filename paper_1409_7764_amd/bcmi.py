@@ -40,10 +40,12 @@ class bc_info(ctypes.Structure):
                 ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
                 ("t_done_ms", ctypes.c_double), ("reached", ctypes.c_uint64), ("examined", ctypes.c_uint64),
                 ("dag_edges", ctypes.c_uint64), ("batch_entries", ctypes.c_uint64),
-                ("batch_edge_visits", ctypes.c_uint64)]
+                ("batch_edge_visits", ctypes.c_uint64), ("batch_cycles", ctypes.c_uint64 * 3)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {k: getattr(self, k) for k, _ in self._fields_}
+        out["batch_cycles"] = list(self.batch_cycles)
+        return out
 
 
 _lib = None

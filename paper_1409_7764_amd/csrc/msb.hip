@@ -13,11 +13,13 @@
 //
 // forward, level d, entry (v, f): for each successor w the lanes of one wavefront test 64
 //   edges at once: dag = f & ~seen[w] are the sources with w at level d+1; they are OR-ed
-//   into nxt[w] (the first writer appends w to the next level's list) and, lane per source,
-//   sig[w][s] += sig[v][s] for s in dag (64-bit integer atomics, issued without waiting for
-//   the old value whenever a bound on sigma proves that no carry can occur; otherwise the
-//   old value is checked and a carry flags that source, which is then recounted exactly by
-//   the per-source kernel in double precision).
+//   into nxt[w] and, lane per source, sig[w][s] += sig[v][s] for s in dag (64-bit integer
+//   atomics, issued without waiting for the old value whenever a bound on sigma proves that
+//   no carry can occur; otherwise the old value is checked and a carry flags that source,
+//   which is then recounted exactly by the per-source kernel in double precision).  No
+//   operation of the expansion waits for a returned value, so a unit costs two dependent
+//   memory round trips.  The level-(d+1) list is then collected by one coalesced pass over
+//   nxt (entries in vertex order), which also folds the masks into seen.
 // backward, level d, entry (v, f): succ = f & nxt[w] are the sources with w one level down;
 //   lane s sums psi_s(w), then delta_s(v) = sigma_s(v) * sum, psi_s(v) is stored over
 //   sigma_s(v), and sum over s != v of delta_s(v) is added to BC[v].  Each (v, s) has one
@@ -207,24 +209,56 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total,
     return before + incl - x;
 }
 
-// wavefront-aggregated append of fresh vertices to the team's level list
-__device__ __forceinline__ void append(TeamCtl* c, uint32_t* lv, bool fresh, uint32_t w) {
-    const uint64_t mask = __ballot(fresh);
-    if (mask) {
-        const unsigned lane = lane_id();
-        const unsigned leader = __builtin_ctzll(mask);
+// Collects a level: every vertex whose next-mask is non-zero becomes an entry (w, mask) of
+// the team's level list; the mask is folded into seen and the next-mask cleared.  Each
+// thread takes kScanUnroll vertices per pass (loads first), each wavefront one list append.
+constexpr int kScanUnroll = 4;
+__device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, uint64_t* seen, uint64_t* nxt,
+                                                  uint32_t* lv, uint64_t* lm, uint32_t first, uint32_t stride,
+                                                  uint32_t n) {
+    const unsigned lane = lane_id();
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint32_t sdeg = 0;
+    for (uint32_t b0 = first; b0 < n; b0 += stride * kScanUnroll) {
+        uint64_t m[kScanUnroll];
+        uint64_t bal[kScanUnroll];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < kScanUnroll; ++j) {
+            const uint32_t w = b0 + j * stride;
+            m[j] = w < n ? nxt[w] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kScanUnroll; ++j) {
+            bal[j] = __ballot(m[j] != 0ull);
+            cnt += (uint32_t)__builtin_popcountll(bal[j]);
+        }
+        if (!cnt) continue;
         uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&c->tail, (uint32_t)__builtin_popcountll(mask));
-        base = __shfl(base, leader, 64);
-        if (fresh) lv[base + (uint32_t)__builtin_popcountll(mask & ((1ull << lane) - 1ull))] = w;
+        if (lane == 0) base = atomicAdd(&c->tail, cnt);
+        base = __shfl(base, 0, 64);
+#pragma unroll
+        for (int j = 0; j < kScanUnroll; ++j) {
+            const uint32_t w = b0 + j * stride;
+            if (m[j]) {
+                const uint32_t pos = base + (uint32_t)__builtin_popcountll(bal[j] & below);
+                lv[pos] = w;
+                lm[pos] = m[j];
+                __hip_atomic_fetch_or((unsigned long long*)&seen[w], (unsigned long long)m[j], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                nxt[w] = 0ull;
+                sdeg += a.row_ptr[w + 1] - a.row_ptr[w];
+            }
+            base += (uint32_t)__builtin_popcountll(bal[j]);
+        }
     }
+    return sdeg;
 }
 
 // forward work unit: up to 64 out-edges [e0, e1) of the level-d entry (v, f)
 template <int WG>
-__device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, TeamCtl* c, uint64_t* seen, uint64_t* nxt,
-                                         uint64_t* sig, uint32_t* lv, uint32_t v, uint64_t f, uint32_t e0,
-                                         uint32_t e1, bool safe) {
+__device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, uint64_t* seen, uint64_t* nxt,
+                                         uint64_t* sig, uint32_t v, uint64_t f, uint32_t e0, uint32_t e1, bool safe) {
     const unsigned lane = lane_id();
     const bool act = (f >> lane) & 1ull;
     const uint32_t e = e0 + lane;
@@ -233,17 +267,16 @@ __device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, TeamCt
     const uint64_t sv = act ? sig[(size_t)v * 64 + lane] : 0ull;
     const uint32_t w = ok ? a.col[e] : 0u;
     uint64_t dag = 0;
-    bool fresh = false;
     if (ok) {
         dag = f & ~seen[w];
         // bits only get set during a level, so a plain read that already shows every bit of
-        // dag (stale reads show fewer) proves the atomic would change nothing and that this
-        // edge is not the vertex's first discovery: skip it (hot vertices get many such edges)
-        if (dag && (dag & ~nxt[w])) fresh = atomicOr((unsigned long long*)&nxt[w], (unsigned long long)dag) == 0ull;
+        // dag (stale reads show fewer) proves the OR would change nothing: skip it
+        if (dag && (dag & ~nxt[w]))
+            __hip_atomic_fetch_or((unsigned long long*)&nxt[w], (unsigned long long)dag, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
     }
     const uint64_t mx = wave_max64(sv);
     if (lane == 0 && mx > L.maxsig) atomicMax((unsigned long long*)&L.maxsig, (unsigned long long)mx);
-    append(c, lv, fresh, w);
     // phase B, lane per source: the unit's DAG edges, compacted in LDS, one row update each
     const uint64_t bal = __ballot(dag != 0ull);
     const uint32_t cnt = (uint32_t)__builtin_popcountll(bal);
@@ -350,6 +383,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     uint32_t reached = 0, dagc = 0, entries = 0;
     uint64_t examined = 0, visits = 0;
     uint32_t n_done = 0, levels_max = 0;
+    uint64_t cyc[3] = {0, 0, 0};   // thread 0: clock cycles in forward, backward, reset
 
     if (tid == 0) {
         L.nhub = 0;
@@ -372,15 +406,13 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
         const uint32_t nl = min(64u, total - base);
         const uint64_t lanes = nl == 64 ? ~0ull : ((1ull << nl) - 1ull);
         const uint32_t my_src = lane < nl ? a.plan[base + lane] : 0xffffffffu;
-        if (leader && wave == 0) {   // level 0: the sources themselves
-            bool fresh = false;
-            if (lane < nl) {
-                fresh = atomicOr((unsigned long long*)&nxt[my_src], (unsigned long long)(1ull << lane)) == 0ull;
-                sig[(size_t)my_src * 64 + lane] = 1ull;
-            }
-            append(ctl, lv, fresh, my_src);
+        if (leader && wave == 0 && lane < nl) {   // level 0: the sources themselves
+            __hip_atomic_fetch_or((unsigned long long*)&nxt[my_src], (unsigned long long)(1ull << lane),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sig[(size_t)my_src * 64 + lane] = 1ull;
         }
         // ---------------- forward sweep ----------------
+        uint64_t t_phase = clock64();
         uint32_t lo = 0, d = 0;
         bool stopped = false;       // every thread takes the same decision from the same values
         bool aborted = false;
@@ -389,31 +421,23 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 aborted = true;
                 break;
             }
-            const uint32_t hi = ld_acq(&ctl->tail);
             if (leader && tid == 0) {
                 ctl->cc = 0;                       // chunk counter of this level's expansion
                 ctl->maxsig[d & 1] = 0;            // filled while expanding level d
-                ctl->sdeg[(d + 1) & 1] = 0;        // filled by the next level's pass
+                ctl->sdeg[(d + 1) & 1] = 0;        // filled by the next level's scan
             }
-            // fix the masks of the level-d entries and fold them into seen
-            uint32_t sdeg = 0;
-            for (uint32_t i = lo + gtid; i < hi; i += gthreads) {
-                const uint32_t w = lv[i];
-                const uint64_t m = nxt[w];
-                lm[i] = m;
-                seen[w] |= m;
-                nxt[w] = 0ull;
-                sdeg += a.row_ptr[w + 1] - a.row_ptr[w];
-            }
+            // level d: the vertices some source reached in the previous expansion
+            uint32_t sdeg = collect_level(a, ctl, seen, nxt, lv, lm, member * WG + tid, gthreads, (uint32_t)n);
             sdeg = wave_sum_u32(sdeg);
             if (lane == 0 && sdeg) atomicAdd(&ctl->sdeg[d & 1], sdeg);
-            if (leader && tid == 0) {
-                lvl[d] = lo;
-                lvl[d + 1] = hi;
-            }
             if (!team_sync(L, ctl, W, a.stats)) {
                 aborted = true;
                 break;
+            }
+            const uint32_t hi = ld_acq(&ctl->tail);
+            if (leader && tid == 0) {
+                lvl[d] = lo;
+                lvl[d + 1] = hi;
             }
             if (hi == lo) break;   // level d is empty: the sweep is over (levels 0..d-1)
             const uint64_t room = (uint64_t)a.cap - hi;
@@ -449,7 +473,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     const uint32_t j = find_owner<WG>(L.off, u);
                     const uint32_t e0 = L.eb[j] + (u - L.off[j]) * 64;
                     const uint32_t e1 = min(L.eb[j] + L.ed[j], e0 + 64);
-                    fwd_unit<WG>(a, L, ctl, seen, nxt, sig, lv, L.ev[j], L.em[j], e0, e1, safe);
+                    fwd_unit<WG>(a, L, seen, nxt, sig, L.ev[j], L.em[j], e0, e1, safe);
                 }
                 __syncthreads();
             }
@@ -463,6 +487,11 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             ++d;
         }
         if (aborted) break;
+        {
+            const uint64_t t = clock64();
+            cyc[0] += t - t_phase;
+            t_phase = t;
+        }
         const uint32_t nlev = d;            // levels 0..nlev-1 hold entries
         const uint32_t n_entries = ld_acq(&ctl->tail);
         const uint64_t ovf = stopped ? lanes : (ld_acq(&ctl->ovf) & lanes);
@@ -579,6 +608,11 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             }
         }
         if (aborted) break;
+        {
+            const uint64_t t = clock64();
+            cyc[1] += t - t_phase;
+            t_phase = t;
+        }
         // ---------------- reset the touched state ----------------
         if (!team_sync(L, ctl, W, a.stats)) break;
         for (uint32_t i = gwave; i < n_entries; i += gwaves) {
@@ -606,6 +640,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             if (!stopped) levels_max = max(levels_max, nlev);
         }
         if (!team_sync(L, ctl, W, a.stats)) break;
+        cyc[2] += clock64() - t_phase;
     }
     // counters of everything this workgroup finished
     const uint32_t r_w = wave_sum_u32(reached), g_w = wave_sum_u32(dagc), n_w = wave_sum_u32(entries);
@@ -625,6 +660,8 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     if (tid == 0) {
         if (n_done) atomicAdd(&a.stats->n_done, n_done);
         if (levels_max) atomicMax(&a.stats->levels_max, levels_max);
+        for (int i = 0; i < 3; ++i)
+            if (cyc[i]) atomicAdd((unsigned long long*)&a.stats->cycles[i], (unsigned long long)cyc[i]);
     }
 }
 
