@@ -88,6 +88,13 @@ constexpr uint32_t kSpinLimit = 1u << 22;  // barrier polls (about 1 us each) be
 __device__ __forceinline__ unsigned lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t x, int k) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, k);
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int k) {
+    const uint32_t lo = readlane_u32((uint32_t)x, k), hi = readlane_u32((uint32_t)(x >> 32), k);
+    return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ double u2d(uint64_t x) { return __longlong_as_double((long long)x); }
 __device__ __forceinline__ uint64_t d2u(double x) { return (uint64_t)__double_as_longlong(x); }
 __device__ __forceinline__ uint64_t wave_max64(uint64_t x) {
@@ -136,8 +143,6 @@ struct MsbLds {
     uint32_t ed[WG];        // out-degree
     int32_t eh[WG];         // accumulator row of a split entry, -1 otherwise
     uint32_t hub_ent[WG];   // accumulator row -> chunk entry
-    uint32_t sw[WG / 64][64];   // per wavefront: compacted (successor, source mask) pairs of a unit
-    uint64_t sm[WG / 64][64];
     uint32_t nhub;
     uint32_t chunk;
     uint32_t ok;            // 0 once the team gave up on a barrier
@@ -277,32 +282,33 @@ __device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, uint64
     }
     const uint64_t mx = wave_max64(sv);
     if (lane == 0 && mx > L.maxsig) atomicMax((unsigned long long*)&L.maxsig, (unsigned long long)mx);
-    // phase B, lane per source: the unit's DAG edges, compacted in LDS, one row update each
-    const uint64_t bal = __ballot(dag != 0ull);
-    const uint32_t cnt = (uint32_t)__builtin_popcountll(bal);
-    const unsigned wv = threadIdx.x / 64;
-    if (dag) {
-        const uint32_t pos = (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
-        L.sw[wv][pos] = w;
-        L.sm[wv][pos] = dag;
-    }
-    __builtin_amdgcn_wave_barrier();
-    bool carry = false;
-    for (uint32_t k = 0; k < cnt; ++k) {
-        const uint32_t wj = L.sw[wv][k];
-        const uint64_t dj = L.sm[wv][k];
-        if ((dj >> lane) & 1ull) {
-            unsigned long long* p = (unsigned long long*)&sig[(size_t)wj * 64 + lane];
-            if (safe) {
-                __hip_atomic_fetch_add(p, (unsigned long long)sv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                const unsigned long long old = atomicAdd(p, (unsigned long long)sv);
+    // phase B, lane per source: one row update per DAG edge of the unit, the edges taken from
+    // the ballot in lane order (their successor and mask read from that lane's registers)
+    uint64_t bal = __ballot(dag != 0ull);
+    // two separate loops: the returning form waits for every old value, the other does not
+    if (safe) {
+        while (bal) {
+            const int k = __builtin_ctzll(bal);
+            bal &= bal - 1ull;
+            const uint32_t wj = readlane_u32(w, k);
+            const uint64_t dj = readlane_u64(dag, k);
+            if ((dj >> lane) & 1ull)
+                __hip_atomic_fetch_add((unsigned long long*)&sig[(size_t)wj * 64 + lane], (unsigned long long)sv,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else {
+        bool carry = false;
+        while (bal) {
+            const int k = __builtin_ctzll(bal);
+            bal &= bal - 1ull;
+            const uint32_t wj = readlane_u32(w, k);
+            const uint64_t dj = readlane_u64(dag, k);
+            if ((dj >> lane) & 1ull) {
+                const unsigned long long old = atomicAdd((unsigned long long*)&sig[(size_t)wj * 64 + lane],
+                                                         (unsigned long long)sv);
                 carry |= old + sv < old;
             }
         }
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (!safe) {
         const uint64_t cm = __ballot(carry);
         if (lane == 0 && cm) atomicOr((unsigned long long*)&L.ovf, (unsigned long long)cm);
     }
@@ -556,30 +562,26 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                             sm = fj & nxt[w];
                         }
                         dagc += (uint32_t)__builtin_popcountll(sm);
-                        // lane per source: sum psi over the unit's successors, loads issued
-                        // eight at a time from the compacted list
-                        const uint64_t bal = __ballot(sm != 0ull);
-                        const uint32_t cnt = (uint32_t)__builtin_popcountll(bal);
-                        if (sm) {
-                            const uint32_t pos = (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
-                            L.sw[wave][pos] = w;
-                            L.sm[wave][pos] = sm;
-                        }
-                        __builtin_amdgcn_wave_barrier();
+                        // lane per source: sum psi over the unit's successors, taken from the
+                        // ballot eight at a time so that eight loads are in flight
+                        uint64_t rem = __ballot(sm != 0ull);
                         double acc = 0.0;
-                        for (uint32_t k = 0; k < cnt; k += 8) {
+                        while (rem) {
                             double x[8];
 #pragma unroll
                             for (int t = 0; t < 8; ++t) {
-                                const bool okt = k + t < cnt;
-                                const uint32_t wt = okt ? L.sw[wave][k + t] : 0u;
-                                const uint64_t mt = okt ? L.sm[wave][k + t] : 0ull;
-                                x[t] = ((mt >> lane) & 1ull) ? u2d(sig[(size_t)wt * 64 + lane]) : 0.0;
+                                x[t] = 0.0;
+                                if (rem) {
+                                    const int k = __builtin_ctzll(rem);
+                                    rem &= rem - 1ull;
+                                    const uint32_t wt = readlane_u32(w, k);
+                                    const uint64_t mt = readlane_u64(sm, k);
+                                    if ((mt >> lane) & 1ull) x[t] = u2d(sig[(size_t)wt * 64 + lane]);
+                                }
                             }
 #pragma unroll
                             for (int t = 0; t < 8; ++t) acc += x[t];
                         }
-                        __builtin_amdgcn_wave_barrier();
                         const int32_t hr = L.eh[j];
                         if (hr < 0) {
                             finish_entry(a, sig, vj, fj, acc, my_src, dj, reached, examined, entries, visits);
