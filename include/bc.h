@@ -107,6 +107,16 @@ BC_API bc_status bc_graph_info(bc_graph g, int32_t* n, int64_t* m);
 BC_API bc_status bc_graph_arrays(bc_graph g, const uint32_t** d_row_ptr, const uint32_t** d_col,
                           const uint32_t** d_csc_ptr, const uint32_t** d_csc_row);
 
+/* Device pointers of the handle's batching order, the order in which the batched path groups
+ * sources (64 per batch).  Vertices are ranked outward from a hub h (the vertex of largest
+ * in-degree among those with out-edges, lowest id on ties) along reversed edges: vertices at
+ * distance k from h (k <= 64) follow every vertex nearer to h and are ranked by (lowest rank
+ * among their successors at distance k-1, floor(log2 out-degree) descending, id); the rest
+ * follow by (floor(log2 out-degree) descending, id), vertices without out-edges last.
+ * d_order: n vertex ids in rank order; d_rank: n ranks (d_rank[d_order[i]] == i).  Both NULL
+ * for a graph without edges.  Read-only, valid until bc_graph_free; either output may be NULL. */
+BC_API bc_status bc_graph_order(bc_graph g, const uint32_t** d_order, const uint32_t** d_rank);
+
 /* Release the handle and every device buffer it owns (waits for the device). */
 BC_API bc_status bc_graph_free(bc_graph g);
 

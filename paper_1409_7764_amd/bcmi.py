@@ -63,6 +63,7 @@ def lib():
         L.bc_build_csr.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, ctypes.POINTER(P)]
         L.bc_graph_info.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
         L.bc_graph_arrays.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)]
+        L.bc_graph_order.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P)]
         L.bc_graph_free.argtypes = [P]
         L.bc_exact.argtypes = [P, P, ctypes.POINTER(bc_tuning), P, ctypes.POINTER(bc_info)]
         L.bc_sampled.argtypes = [P, P, ctypes.c_int32, P, ctypes.POINTER(bc_tuning), P, ctypes.POINTER(bc_info)]
@@ -74,7 +75,8 @@ def lib():
         L.bc_serve_submit.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_uint64)]
         L.bc_serve_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(bc_info)]
         L.bc_serve_destroy.argtypes = [P]
-        for name in ["bc_build_csr", "bc_graph_info", "bc_graph_arrays", "bc_graph_free", "bc_exact", "bc_sampled",
+        for name in ["bc_build_csr", "bc_graph_info", "bc_graph_arrays", "bc_graph_order", "bc_graph_free", "bc_exact",
+                     "bc_sampled",
                      "bc_sssp", "bc_batch", "bc_tune", "bc_serve_create", "bc_serve_submit", "bc_serve_poll",
                      "bc_serve_destroy"]:
             getattr(L, name).restype = ctypes.c_int32
@@ -146,6 +148,21 @@ class Graph:
             if sz:
                 torch.cuda.synchronize()
                 _copy_device(t.data_ptr(), p.value, 4 * sz)
+            out.append(t.cpu().to(torch.int64) & 0xFFFFFFFF)
+        return tuple(out)
+
+
+    def order(self):
+        """(order, rank) of the batching order as int64 CPU tensors, or None without edges."""
+        po, pr = P(), P()
+        _check(lib().bc_graph_order(self.handle, ctypes.byref(po), ctypes.byref(pr)))
+        if not po.value:
+            return None
+        out = []
+        for p in (po, pr):
+            t = torch.empty(self.n, dtype=torch.int32, device="cuda")
+            torch.cuda.synchronize()
+            _copy_device(t.data_ptr(), p.value, 4 * self.n)
             out.append(t.cpu().to(torch.int64) & 0xFFFFFFFF)
         return tuple(out)
 

@@ -26,6 +26,8 @@ Graph::~Graph() {
     if (perm) (void)hipFree(perm);
     if (iperm) (void)hipFree(iperm);
     if (prow) (void)hipFree(prow);
+    if (rank) (void)hipFree(rank);
+    if (order) (void)hipFree(order);
     if (pcol) (void)hipFree(pcol);
     if (stats) (void)hipFree(stats);
     (void)hipSetDevice(prev);
@@ -176,6 +178,14 @@ bc_status bc_graph_arrays(bc_graph gh, const uint32_t** row_ptr, const uint32_t*
         if (col) *col = g->col;
         if (csc_ptr) *csc_ptr = g->csc_ptr;
         if (csc_row) *csc_row = g->csc_row;
+    });
+}
+
+bc_status bc_graph_order(bc_graph gh, const uint32_t** order, const uint32_t** rank) {
+    return guarded([&] {
+        Graph* g = as_graph(gh);
+        if (order) *order = g->order;
+        if (rank) *rank = g->rank;
     });
 }
 

@@ -96,6 +96,10 @@ struct Graph {
     uint32_t* iperm = nullptr;     // kernel id -> caller id
     uint32_t* prow = nullptr;      // kernel CSR (n+1), successors sorted per row
     uint32_t* pcol = nullptr;      // m
+    // batching order of the batched path (caller ids): rank[v] = position of v in `order`,
+    // vertices with out-edges first (null when not built)
+    uint32_t* rank = nullptr;      // n
+    uint32_t* order = nullptr;     // n
     const uint32_t* krow() const { return prow ? prow : row_ptr; }
     const uint32_t* kcol() const { return pcol ? pcol : col; }
     uint32_t max_out_degree = 0;

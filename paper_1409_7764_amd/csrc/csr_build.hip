@@ -280,9 +280,164 @@ __global__ void k_count_zero(const uint32_t* deg, uint64_t N, uint32_t* out) {
     if (lane_id() == 0 && c) atomicAdd(out, c);
 }
 
+// --- 7. batching order ---------------------------------------------------------------------
+// Sources batched together gain when their shortest-path DAGs share edges.  The order ranks
+// vertices outward from a hub h (largest in-degree among vertices with out-edges) over reversed
+// edges: level k holds the vertices at distance k from h, ranked after every lower level, by
+// (lowest rank among their successors on level k-1, out-degree bucket, id).  Sources whose
+// paths towards h run through the same vertices then sit next to each other, and so do sources
+// with a common successor.  Vertices that do not reach h within kOrderLevels come last, by
+// out-degree bucket (out-degree 0 last of all).
+constexpr uint32_t kInf = 0xffffffffu;
+constexpr int kOrderLevels = 64;
+
+__device__ __forceinline__ uint32_t deg_bucket(uint32_t deg) { return deg ? (uint32_t)__clz(deg) : 32u; }
+
+__global__ void k_hub_key(const uint32_t* row_ptr, const uint32_t* csc_ptr, uint32_t n, unsigned long long* best) {
+    unsigned long long b = 0;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (row_ptr[v + 1] > row_ptr[v]) {
+            const unsigned long long key = ((unsigned long long)(csc_ptr[v + 1] - csc_ptr[v]) << 32) | (kInf - v);
+            b = key > b ? key : b;
+        }
+    for (int d = 32; d > 0; d >>= 1) {
+        const unsigned long long y = (unsigned long long)__shfl_xor((long long)b, d, 64);
+        b = y > b ? y : b;
+    }
+    if (lane_id() == 0 && b) atomicMax(best, b);
+}
+
+__global__ void k_order_init(uint32_t* hdist, uint32_t* rank, uint32_t* order, uint32_t n,
+                             const unsigned long long* best, uint32_t* frontier) {
+    const uint32_t hub = kInf - (uint32_t)(*best & 0xffffffffull);
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        hdist[v] = v == hub ? 0u : kInf;
+        rank[v] = v == hub ? 0u : kInf;
+        if (v == hub) {
+            order[0] = hub;
+            frontier[0] = hub;
+        }
+    }
+}
+
+// one wavefront per frontier vertex u: claims its unvisited predecessors for level k
+__global__ void k_order_discover(const uint32_t* csc_ptr, const uint32_t* csc_row, const uint32_t* frontier,
+                                 uint32_t nf, uint32_t k, uint32_t* hdist, uint32_t* next, uint32_t* next_count) {
+    const unsigned lane = lane_id();
+    const uint32_t waves = gridDim.x * (blockDim.x / 64);
+    for (uint32_t i = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; i < nf; i += waves) {
+        const uint32_t u = frontier[i];
+        for (uint32_t e0 = csc_ptr[u]; e0 < csc_ptr[u + 1]; e0 += 64) {
+            const uint32_t e = e0 + lane;
+            bool take = false;
+            uint32_t v = 0;
+            if (e < csc_ptr[u + 1]) {
+                v = csc_row[e];
+                take = hdist[v] == kInf && atomicCAS(&hdist[v], kInf, k) == kInf;
+            }
+            const uint64_t mask = __ballot(take);
+            if (mask) {
+                const unsigned leader = __builtin_ctzll(mask);
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(next_count, (uint32_t)__builtin_popcountll(mask));
+                base = __shfl(base, leader, 64);
+                if (take) next[base + __builtin_popcountll(mask & ((1ull << lane) - 1))] = v;
+            }
+        }
+    }
+}
+
+__global__ void k_order_keys(const uint32_t* row_ptr, const uint32_t* col, const uint32_t* level,
+                             const uint32_t* count, uint32_t k, const uint32_t* hdist, const uint32_t* rank, int vbits,
+                             uint64_t* keys) {
+    const uint32_t nl = *count;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
+        const uint32_t v = level[i];
+        uint32_t best = kInf;
+        for (uint32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            const uint32_t u = col[e];
+            if (hdist[u] == k - 1) best = min(best, rank[u]);
+        }
+        const uint32_t deg = row_ptr[v + 1] - row_ptr[v];
+        keys[i] = ((uint64_t)best << (vbits + 6)) | ((uint64_t)deg_bucket(deg) << vbits) | v;
+    }
+}
+
+// the vertices left without a rank, keyed by out-degree bucket
+__global__ void k_order_rest(const uint32_t* row_ptr, const uint32_t* rank, uint32_t n, int vbits, uint64_t* keys,
+                             uint32_t* count) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (rank[v] == kInf) keys[atomicAdd(count, 1u)] = ((uint64_t)deg_bucket(row_ptr[v + 1] - row_ptr[v]) << vbits) | v;
+}
+
+__global__ void k_order_assign(const uint64_t* keys, const uint32_t* count, uint32_t base, int vbits, uint32_t* rank,
+                               uint32_t* order, uint32_t* frontier) {
+    const uint32_t nl = *count;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)(keys[i] & ((1ull << vbits) - 1));
+        rank[v] = base + i;
+        order[base + i] = v;
+        if (frontier) frontier[i] = v;
+    }
+}
+
 inline unsigned grid_for(uint64_t N, int block) { return (unsigned)std::max<uint64_t>(1, (N + block - 1) / block); }
 
 }  // namespace
+
+// Ranks the vertices for batching (see the batching order above): g.rank[v] and g.order,
+// the vertices in rank order.  Needs the CSR and CSC; ids of up to 29 bits.
+static void build_order(Graph& g, int vbits, hipStream_t st) {
+    const uint32_t n = (uint32_t)g.n;
+    if (g.m == 0 || 2 * vbits + 6 > 64) return;
+    BC_HIP_TRY(hipMalloc((void**)&g.rank, sizeof(uint32_t) * n));
+    BC_HIP_TRY(hipMalloc((void**)&g.order, sizeof(uint32_t) * n));
+    uint32_t *hdist = nullptr, *fa = nullptr, *fb = nullptr, *cnt = nullptr;
+    uint64_t *ka = nullptr, *kb = nullptr;
+    BC_HIP_TRY(hipMallocAsync((void**)&hdist, sizeof(uint32_t) * n, st));
+    BC_HIP_TRY(hipMallocAsync((void**)&fa, sizeof(uint32_t) * n, st));
+    BC_HIP_TRY(hipMallocAsync((void**)&fb, sizeof(uint32_t) * n, st));
+    BC_HIP_TRY(hipMallocAsync((void**)&ka, sizeof(uint64_t) * n, st));
+    BC_HIP_TRY(hipMallocAsync((void**)&kb, sizeof(uint64_t) * n, st));
+    BC_HIP_TRY(hipMallocAsync((void**)&cnt, sizeof(uint32_t) * 4 * (kOrderLevels + 2), st));
+    BC_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * 4 * (kOrderLevels + 2), st));
+    unsigned long long* best = (unsigned long long*)cnt;   // cnt[0..1]
+    const unsigned gn = std::min<unsigned>(grid_for(n, 256), 4096);
+    hipLaunchKernelGGL(k_hub_key, dim3(gn), dim3(256), 0, st, g.row_ptr, g.csc_ptr, n, best);
+    hipLaunchKernelGGL(k_order_init, dim3(gn), dim3(256), 0, st, hdist, g.rank, g.order, n, best, fa);
+    BC_HIP_TRY(hipGetLastError());
+    uint32_t placed = 1, nf = 1;
+    // level k's size lands in cnt[2 + k]
+    for (uint32_t k = 1; k <= (uint32_t)kOrderLevels && nf > 0; ++k) {
+        uint32_t* c = cnt + 2 + k;
+        const unsigned gd = std::min<unsigned>(std::max<unsigned>(1, (nf + 3) / 4), 8192);
+        hipLaunchKernelGGL(k_order_discover, dim3(gd), dim3(256), 0, st, g.csc_ptr, g.csc_row, fa, nf, k, hdist, fb, c);
+        BC_HIP_TRY(hipGetLastError());
+        uint32_t nl = 0;
+        BC_HIP_TRY(hipMemcpyAsync(&nl, c, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        BC_HIP_TRY(hipStreamSynchronize(st));
+        if (nl == 0) break;
+        const unsigned gl = std::min<unsigned>(grid_for(nl, 256), 4096);
+        hipLaunchKernelGGL(k_order_keys, dim3(gl), dim3(256), 0, st, g.row_ptr, g.col, fb, c, k, hdist, g.rank, vbits, ka);
+        BC_HIP_TRY(hipGetLastError());
+        uint64_t* sorted = radix_sort(ka, kb, nl, 2 * vbits + 6, st);
+        hipLaunchKernelGGL(k_order_assign, dim3(gl), dim3(256), 0, st, sorted, c, placed, vbits, g.rank, g.order, fa);
+        BC_HIP_TRY(hipGetLastError());
+        placed += nl;
+        nf = nl;
+    }
+    if (placed < n) {
+        uint32_t* c = cnt + 2 + kOrderLevels + 1;
+        BC_HIP_TRY(hipMemsetAsync(c, 0, sizeof(uint32_t), st));
+        hipLaunchKernelGGL(k_order_rest, dim3(gn), dim3(256), 0, st, g.row_ptr, g.rank, n, vbits, ka, c);
+        BC_HIP_TRY(hipGetLastError());
+        uint64_t* sorted = radix_sort(ka, kb, n - placed, vbits + 6, st);
+        hipLaunchKernelGGL(k_order_assign, dim3(gn), dim3(256), 0, st, sorted, c, placed, vbits, g.rank, g.order,
+                           (uint32_t*)nullptr);
+        BC_HIP_TRY(hipGetLastError());
+    }
+    for (void* q : {(void*)hdist, (void*)fa, (void*)fb, (void*)ka, (void*)kb, (void*)cnt}) BC_HIP_TRY(hipFreeAsync(q, st));
+}
 
 void build_csr_device(int32_t n, int64_t m_in, const uint32_t* d_src, const uint32_t* d_dst, hipStream_t st,
                       Graph& g) {
@@ -407,6 +562,8 @@ void build_csr_device(int32_t n, int64_t m_in, const uint32_t* d_src, const uint
     BC_HIP_TRY(hipFreeAsync(counters, st));
     BC_HIP_TRY(hipStreamSynchronize(st));
     g.m = m;
+    build_order(g, vbits, st);
+    BC_HIP_TRY(hipStreamSynchronize(st));
     g.max_out_degree = h[3];
     g.max_in_degree = h[2];
     g.zero_out_degree = h[1];

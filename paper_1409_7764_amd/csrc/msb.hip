@@ -27,9 +27,11 @@
 //   pieces; their partial sums meet in a per-batch accumulator row before the owner
 //   finishes the vertex.
 //
-// Sources are grouped by out-degree (a cheap proxy for their distance to the dense core of
-// a scale-free graph), which aligns the batch's levels; sources without out-edges reach no
-// vertex and contribute nothing, so they are not run.
+// Sources are batched in the graph's batching order (built with the CSR: vertices ranked
+// outward from a hub over reversed edges, grouped by the successor through which they reach
+// it).  Sources batched that way share most of their DAG edges and reach vertices at the same
+// levels, so a row update carries more sources and touches fewer sectors of the row.  Sources
+// without out-edges reach no vertex and contribute nothing, so they are not run.
 #include "bc_internal.h"
 
 #include <algorithm>
@@ -667,54 +669,88 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     }
 }
 
-// ---- source plan: valid sources with out-edges, grouped by out-degree (largest first) ----
-constexpr int kPlanBuckets = 33;   // bucket q = count of leading zeros of the out-degree; 32 = no out-edges
+// ---- source plan: valid sources with out-edges, in the graph's batching order ----
+// All vertices as sources: the plan is the order itself (its vertices with out-edges come
+// first).  A source list is counting-sorted by rank into kPlanBuckets buckets of consecutive
+// ranks (exact order for graphs of up to kPlanBuckets vertices).
+constexpr uint32_t kPlanBuckets = 65536;
 
-__global__ void k_plan_hist(const uint32_t* row_ptr, const uint32_t* srcs, const uint32_t* perm, uint32_t k,
-                            uint32_t n, uint32_t* hist, CallStats* stats) {
-    __shared__ uint32_t h[kPlanBuckets];
-    if (threadIdx.x < kPlanBuckets) h[threadIdx.x] = 0;
-    __syncthreads();
-    uint32_t bad = 0;
+__device__ __forceinline__ uint32_t plan_bucket(const uint32_t* rank, uint32_t s, uint32_t n, uint32_t nb) {
+    const uint32_t r = rank ? rank[s] : s;
+    return (uint32_t)(((uint64_t)r * nb) / n);
+}
+
+__global__ void k_plan_all(const uint32_t* order, uint32_t n, uint32_t active, const uint32_t* perm, uint32_t* plan,
+                           uint32_t* plan_count, CallStats* stats) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < active; i += gridDim.x * blockDim.x) {
+        const uint32_t s = order ? order[i] : i;
+        plan[i] = perm ? perm[s] : s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        plan_count[0] = active;
+        // sources without out-edges: finished here (they reach only themselves)
+        const uint32_t idle = n - active;
+        stats->n_done += idle;
+        stats->reached += idle;
+        if (idle && stats->levels_max < 1) stats->levels_max = 1;
+    }
+}
+
+// hist[0..nb): sources per bucket; hist[nb]: sources without out-edges
+__global__ void k_plan_hist(const uint32_t* row_ptr, const uint32_t* rank, const uint32_t* srcs, uint32_t k,
+                            uint32_t n, uint32_t nb, uint32_t* hist, CallStats* stats) {
+    uint32_t bad = 0, idle = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-        uint32_t s = srcs ? srcs[i] : i;
+        const uint32_t s = srcs ? srcs[i] : i;
         if (s >= n) {
             ++bad;
-            continue;
+        } else if (row_ptr[s + 1] == row_ptr[s]) {
+            ++idle;
+        } else {
+            atomicAdd(&hist[plan_bucket(rank, s, n, nb)], 1u);
         }
-        if (srcs && perm) s = perm[s];
-        const uint32_t deg = row_ptr[s + 1] - row_ptr[s];
-        atomicAdd(&h[deg ? __clz(deg) : 32], 1u);
     }
-    __syncthreads();
-    if (threadIdx.x < kPlanBuckets && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
     if (bad) atomicAdd(&stats->bad_source, bad);
+    if (idle) atomicAdd(&hist[nb], idle);
 }
 
-__global__ void k_plan_scan(const uint32_t* hist, uint32_t* cursor, uint32_t* plan_count, CallStats* stats) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint32_t run = 0;
-    for (int q = 0; q < kPlanBuckets; ++q) {
-        cursor[q] = run;
-        run += hist[q];
+// one workgroup of 1024 threads: exclusive scan of hist[0..nb) in place
+__global__ void __launch_bounds__(1024) k_plan_scan(uint32_t* hist, uint32_t nb, uint32_t* plan_count,
+                                                    CallStats* stats) {
+    __shared__ uint32_t part[1024];
+    const uint32_t t = threadIdx.x, per = (nb + 1023) / 1024;
+    const uint32_t b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+    uint32_t sum = 0;
+    for (uint32_t i = b0; i < b1; ++i) sum += hist[i];
+    part[t] = sum;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {   // inclusive Hillis-Steele scan of the parts
+        const uint32_t y = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
     }
-    const uint32_t idle = hist[kPlanBuckets - 1];
-    plan_count[0] = run - idle;
-    // sources without out-edges: finished here (they reach only themselves)
-    stats->n_done += idle;
-    stats->reached += idle;
-    if (idle && stats->levels_max < 1) stats->levels_max = 1;
+    uint32_t run = part[t] - sum;
+    for (uint32_t i = b0; i < b1; ++i) {
+        const uint32_t c = hist[i];
+        hist[i] = run;
+        run += c;
+    }
+    if (t == 1023) {
+        plan_count[0] = part[1023];
+        const uint32_t idle = hist[nb];
+        stats->n_done += idle;
+        stats->reached += idle;
+        if (idle && stats->levels_max < 1) stats->levels_max = 1;
+    }
 }
 
-__global__ void k_plan_scatter(const uint32_t* row_ptr, const uint32_t* srcs, const uint32_t* perm, uint32_t k,
-                               uint32_t n, uint32_t* cursor, uint32_t* plan) {
+__global__ void k_plan_scatter(const uint32_t* row_ptr, const uint32_t* rank, const uint32_t* srcs, uint32_t k,
+                               uint32_t n, uint32_t nb, const uint32_t* perm, uint32_t* cursor, uint32_t* plan) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-        uint32_t s = srcs ? srcs[i] : i;
-        if (s >= n) continue;
-        if (srcs && perm) s = perm[s];
-        const uint32_t deg = row_ptr[s + 1] - row_ptr[s];
-        if (!deg) continue;
-        plan[atomicAdd(&cursor[__clz(deg)], 1u)] = s;
+        const uint32_t s = srcs ? srcs[i] : i;
+        if (s >= n || row_ptr[s + 1] == row_ptr[s]) continue;
+        plan[atomicAdd(&cursor[plan_bucket(rank, s, n, nb)], 1u)] = perm ? perm[s] : s;
     }
 }
 
@@ -761,7 +797,8 @@ struct MsbPool {
     uint32_t* plan = nullptr;       // [plan_cap]
     uint32_t* retry = nullptr;      // [plan_cap]
     uint32_t plan_cap = 0;
-    uint32_t* small = nullptr;      // hist[33] cursor[33] plan_count retry_count
+    uint32_t* small = nullptr;      // [80] plan_count, [81] retry_count
+    uint32_t* bhist = nullptr;      // [kPlanBuckets + 1] plan histogram / cursors
 };
 
 size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels) {
@@ -771,7 +808,7 @@ size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels) {
 
 void msb_pool_free(MsbPool& p) {
     for (void* q : {(void*)p.ctl, (void*)p.seen, (void*)p.nxt, (void*)p.sig, (void*)p.lst_m, (void*)p.hacc,
-                    (void*)p.lst_v, (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small})
+                    (void*)p.lst_v, (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small, (void*)p.bhist})
         if (q) (void)hipFree(q);
     p = MsbPool{};
 }
@@ -815,6 +852,7 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     BC_HIP_TRY(hipMalloc((void**)&p.plan, (size_t)p.plan_cap * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.retry, (size_t)p.plan_cap * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.small, 128 * 4));
+    BC_HIP_TRY(hipMalloc((void**)&p.bhist, (size_t)(kPlanBuckets + 1) * 4));
     const size_t words = (size_t)teams * p.mask_stride;
     const unsigned g1 = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.seen, words);
@@ -858,22 +896,32 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     const int grid = (int)max_wgs;
     msb_pool_ensure(p, n, (int)teams, grid, cap, max_levels, (uint32_t)wg, std::max<uint32_t>(k, n), st);
 
-    uint32_t* hist = p.small;
-    uint32_t* cursor = p.small + 40;
     uint32_t* plan_count = p.small + 80;
     uint32_t* retry_count = p.small + 81;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, st, p.small, 128u);
-    const uint32_t items = sources ? k : n;
-    const unsigned gp = std::max(1u, std::min<unsigned>((items + 255) / 256, 2048));
     // the batched kernel runs on the caller's numbering unless BCMI_MSB_RELABEL=1
     const char* mr = std::getenv("BCMI_MSB_RELABEL");
     const bool rel = mr && mr[0] == '1' && g.perm;
     const uint32_t* krow = rel ? g.prow : g.row_ptr;
     const uint32_t* kcol = rel ? g.pcol : g.col;
     const uint32_t* kperm = rel ? g.perm : nullptr;
-    hipLaunchKernelGGL(k_plan_hist, dim3(gp), dim3(256), 0, st, krow, sources, kperm, items, n, hist, stats);
-    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, st, hist, cursor, plan_count, stats);
-    hipLaunchKernelGGL(k_plan_scatter, dim3(gp), dim3(256), 0, st, krow, sources, kperm, items, n, cursor, p.plan);
+    if (!sources && g.order) {
+        const uint32_t active = (uint32_t)(g.n - g.zero_out_degree);
+        const unsigned gp = std::max(1u, std::min<unsigned>((active + 255) / 256, 2048));
+        hipLaunchKernelGGL(k_plan_all, dim3(gp), dim3(256), 0, st, g.order, n, active, kperm, p.plan, plan_count,
+                           stats);
+    } else {
+        const uint32_t nb = std::min<uint32_t>(n, kPlanBuckets);
+        const uint32_t items = sources ? k : n;
+        const unsigned gp = std::max(1u, std::min<unsigned>((items + 255) / 256, 2048));
+        hipLaunchKernelGGL(k_zero_u32, dim3(std::max(1u, std::min<unsigned>((nb + 256) / 256, 1024))), dim3(256), 0, st,
+                           p.bhist, nb + 1);
+        hipLaunchKernelGGL(k_plan_hist, dim3(gp), dim3(256), 0, st, g.row_ptr, g.rank, sources, items, n, nb, p.bhist,
+                           stats);
+        hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, st, p.bhist, nb, plan_count, stats);
+        hipLaunchKernelGGL(k_plan_scatter, dim3(gp), dim3(256), 0, st, g.row_ptr, g.rank, sources, items, n, nb,
+                           kperm, p.bhist, p.plan);
+    }
     BC_HIP_TRY(hipGetLastError());
 
     MsbArgs a{};
