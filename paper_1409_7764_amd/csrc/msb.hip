@@ -8,6 +8,7 @@
 //   seen[v]     sources that reached v at a level <= d         (64-bit mask)
 //   nxt[v]      sources reaching v at level d+1 (forward); the level-(d+1) masks, scattered,
 //               during the backward sweep
+//               (seen and nxt of a vertex share one 16-byte record: one gather per edge)
 //   sig[v][s]   shortest-path count sigma_s(v) (uint64); after v's level has been finished
 //               in the backward sweep, psi_s(v) = (1 + delta_s(v)) / sigma_s(v) (double bits)
 //
@@ -64,15 +65,14 @@ struct MsbArgs {
     uint32_t* retry_count;
     CallStats* stats;
     TeamCtl* ctl;                // [teams]
-    uint64_t* seen;              // [teams][n]
-    uint64_t* nxt;               // [teams][n]
+    uint64_t* masks;             // [teams][n][2]: {seen, nxt} per vertex
     uint64_t* sig;               // [teams][n][64]
     double* hacc;                // [workgroups][hub_rows][64]
     uint32_t* lst_v;             // [teams][cap]
     uint64_t* lst_m;             // [teams][cap]
     uint32_t* lvl;               // [teams][max_levels + 2]
     int32_t n;
-    uint64_t mask_stride;        // elements between two teams' seen / nxt arrays
+    uint64_t mask_stride;        // elements between two teams' mask arrays
     uint64_t sig_stride;         // elements between two teams' count rows
     uint32_t cap;
     uint32_t max_levels;
@@ -134,6 +134,17 @@ template <class T>
 __device__ __forceinline__ void st_rel(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// per-vertex masks of one team: {seen, nxt} in one 16-byte record
+struct Masks {
+    uint64_t* p;
+    __device__ __forceinline__ uint64_t& seen(uint32_t v) const { return p[2 * (size_t)v]; }
+    __device__ __forceinline__ uint64_t& nxt(uint32_t v) const { return p[2 * (size_t)v + 1]; }
+    __device__ __forceinline__ ulonglong2 both(uint32_t v) const { return reinterpret_cast<const ulonglong2*>(p)[v]; }
+    __device__ __forceinline__ void clear(uint32_t v) const {
+        reinterpret_cast<ulonglong2*>(p)[v] = make_ulonglong2(0ull, 0ull);
+    }
+};
 
 template <int WG>
 struct MsbLds {
@@ -220,8 +231,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total,
 // the team's level list; the mask is folded into seen and the next-mask cleared.  Each
 // thread takes kScanUnroll vertices per pass (loads first), each wavefront one list append.
 constexpr int kScanUnroll = 4;
-__device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, uint64_t* seen, uint64_t* nxt,
-                                                  uint32_t* lv, uint64_t* lm, uint32_t first, uint32_t stride,
+__device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, const Masks mk, uint32_t* lv, uint64_t* lm, uint32_t first, uint32_t stride,
                                                   uint32_t n) {
     const unsigned lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
@@ -233,7 +243,7 @@ __device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, 
 #pragma unroll
         for (int j = 0; j < kScanUnroll; ++j) {
             const uint32_t w = b0 + j * stride;
-            m[j] = w < n ? nxt[w] : 0ull;
+            m[j] = w < n ? mk.nxt(w) : 0ull;
         }
 #pragma unroll
         for (int j = 0; j < kScanUnroll; ++j) {
@@ -251,9 +261,9 @@ __device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, 
                 const uint32_t pos = base + (uint32_t)__builtin_popcountll(bal[j] & below);
                 lv[pos] = w;
                 lm[pos] = m[j];
-                __hip_atomic_fetch_or((unsigned long long*)&seen[w], (unsigned long long)m[j], __ATOMIC_RELAXED,
+                __hip_atomic_fetch_or((unsigned long long*)&mk.seen(w), (unsigned long long)m[j], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
-                nxt[w] = 0ull;
+                mk.nxt(w) = 0ull;
                 sdeg += a.row_ptr[w + 1] - a.row_ptr[w];
             }
             base += (uint32_t)__builtin_popcountll(bal[j]);
@@ -264,8 +274,7 @@ __device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, 
 
 // forward work unit: up to 64 out-edges [e0, e1) of the level-d entry (v, f)
 template <int WG>
-__device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, uint64_t* seen, uint64_t* nxt,
-                                         uint64_t* sig, uint32_t v, uint64_t f, uint32_t e0, uint32_t e1, bool safe) {
+__device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, const Masks mk, uint64_t* sig, uint32_t v, uint64_t f, uint32_t e0, uint32_t e1, bool safe) {
     const unsigned lane = lane_id();
     const bool act = (f >> lane) & 1ull;
     const uint32_t e = e0 + lane;
@@ -275,11 +284,12 @@ __device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, uint64
     const uint32_t w = ok ? a.col[e] : 0u;
     uint64_t dag = 0;
     if (ok) {
-        dag = f & ~seen[w];
+        const ulonglong2 q = mk.both(w);
+        dag = f & ~q.x;
         // bits only get set during a level, so a plain read that already shows every bit of
         // dag (stale reads show fewer) proves the OR would change nothing: skip it
-        if (dag && (dag & ~nxt[w]))
-            __hip_atomic_fetch_or((unsigned long long*)&nxt[w], (unsigned long long)dag, __ATOMIC_RELAXED,
+        if ((dag & ~q.y) != 0ull)   // no short-circuit: keeps the record one 16-byte load
+            __hip_atomic_fetch_or((unsigned long long*)&mk.nxt(w), (unsigned long long)dag, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
     }
     const uint64_t mx = wave_max64(sv);
@@ -316,17 +326,17 @@ __device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, uint64
     }
 }
 
-// finishes entry (v, f) of level d with the summed successor psi in `acc`
+// finishes entry (v, f) of level d with the summed successor psi in `acc`; `count` is this
+// lane's sigma_s(v), read by the caller
 __device__ __forceinline__ void finish_entry(const MsbArgs& a, uint64_t* sig, uint32_t v, uint64_t f, double acc,
-                                             uint32_t my_src, uint32_t deg, uint32_t& reached, uint64_t& examined,
-                                             uint32_t& entries, uint64_t& visits) {
+                                             uint64_t count, uint32_t my_src, uint32_t deg, uint32_t& reached,
+                                             uint64_t& examined, uint32_t& entries, uint64_t& visits) {
     const unsigned lane = lane_id();
     double c = 0.0;
     if ((f >> lane) & 1ull) {
-        uint64_t* cell = &sig[(size_t)v * 64 + lane];
-        const double sigma = (double)*cell;
+        const double sigma = (double)count;
         const double delta = sigma * acc;
-        *cell = d2u((1.0 + delta) / sigma);
+        sig[(size_t)v * 64 + lane] = d2u((1.0 + delta) / sigma);
         if (my_src != v) c = delta;
     }
     c = wave_sum(c);
@@ -379,8 +389,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     const bool leader = member == 0;
     TeamCtl* ctl = a.ctl + team;
     const size_t n = (size_t)a.n;
-    uint64_t* seen = a.seen + (size_t)team * a.mask_stride;
-    uint64_t* nxt = a.nxt + (size_t)team * a.mask_stride;
+    const Masks mk{a.masks + (size_t)team * a.mask_stride};
     uint64_t* sig = a.sig + (size_t)team * a.sig_stride;
     double* hacc = a.hacc + (size_t)blockIdx.x * a.hub_rows * 64;
     uint32_t* lv = a.lst_v + (size_t)team * a.cap;
@@ -415,7 +424,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
         const uint64_t lanes = nl == 64 ? ~0ull : ((1ull << nl) - 1ull);
         const uint32_t my_src = lane < nl ? a.plan[base + lane] : 0xffffffffu;
         if (leader && wave == 0 && lane < nl) {   // level 0: the sources themselves
-            __hip_atomic_fetch_or((unsigned long long*)&nxt[my_src], (unsigned long long)(1ull << lane),
+            __hip_atomic_fetch_or((unsigned long long*)&mk.nxt(my_src), (unsigned long long)(1ull << lane),
                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             sig[(size_t)my_src * 64 + lane] = 1ull;
         }
@@ -435,7 +444,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 ctl->sdeg[(d + 1) & 1] = 0;        // filled by the next level's scan
             }
             // level d: the vertices some source reached in the previous expansion
-            uint32_t sdeg = collect_level(a, ctl, seen, nxt, lv, lm, member * WG + tid, gthreads, (uint32_t)n);
+            uint32_t sdeg = collect_level(a, ctl, mk, lv, lm, member * WG + tid, gthreads, (uint32_t)n);
             sdeg = wave_sum_u32(sdeg);
             if (lane == 0 && sdeg) atomicAdd(&ctl->sdeg[d & 1], sdeg);
             if (!team_sync(L, ctl, W, a.stats)) {
@@ -481,7 +490,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     const uint32_t j = find_owner<WG>(L.off, u);
                     const uint32_t e0 = L.eb[j] + (u - L.off[j]) * 64;
                     const uint32_t e1 = min(L.eb[j] + L.ed[j], e0 + 64);
-                    fwd_unit<WG>(a, L, seen, nxt, sig, L.ev[j], L.em[j], e0, e1, safe);
+                    fwd_unit<WG>(a, L, mk, sig, L.ev[j], L.em[j], e0, e1, safe);
                 }
                 __syncthreads();
             }
@@ -514,7 +523,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 const uint32_t lo_d = lvl[dd], hi_d = lvl[dd + 1];
                 const uint32_t lo_n = lvl[dd + 1], hi_n = lvl[dd + 2];
                 if (leader && tid == 0) ctl->cc = 0;
-                for (uint32_t i = lo_n + gtid; i < hi_n; i += gthreads) nxt[lv[i]] = lm[i] & ~ovf;
+                for (uint32_t i = lo_n + gtid; i < hi_n; i += gthreads) mk.nxt(lv[i]) = lm[i] & ~ovf;
                 if (!team_sync(L, ctl, W, a.stats)) {
                     aborted = true;
                     break;
@@ -557,11 +566,15 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                         const uint32_t e0 = L.eb[j] + (u - L.off[j]) * 64;
                         const uint32_t e1 = min(L.eb[j] + dj, e0 + 64);
                         const uint32_t e = e0 + lane;
+                        const int32_t hr = L.eh[j];
+                        // the entry's own counts, read early when this unit finishes the entry
+                        const uint64_t cnt_v =
+                            (hr < 0 && ((fj >> lane) & 1ull)) ? sig[(size_t)vj * 64 + lane] : 0ull;
                         uint32_t w = 0;
                         uint64_t sm = 0;
                         if (e < e1) {
                             w = a.col[e];
-                            sm = fj & nxt[w];
+                            sm = fj & mk.nxt(w);
                         }
                         dagc += (uint32_t)__builtin_popcountll(sm);
                         // lane per source: sum psi over the unit's successors, taken from the
@@ -584,9 +597,8 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
 #pragma unroll
                             for (int t = 0; t < 8; ++t) acc += x[t];
                         }
-                        const int32_t hr = L.eh[j];
                         if (hr < 0) {
-                            finish_entry(a, sig, vj, fj, acc, my_src, dj, reached, examined, entries, visits);
+                            finish_entry(a, sig, vj, fj, acc, cnt_v, my_src, dj, reached, examined, entries, visits);
                         } else if (((fj >> lane) & 1ull) && acc != 0.0) {
                             unsafeAtomicAdd(&hacc[(size_t)hr * 64 + lane], acc);
                         }
@@ -597,7 +609,10 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     const uint32_t nh = L.nhub;
                     for (uint32_t h = wave; h < nh; h += NW) {
                         const uint32_t j = L.hub_ent[h];
-                        finish_entry(a, sig, L.ev[j], L.em[j], hacc[(size_t)h * 64 + lane], my_src, L.ed[j], reached,
+                        const uint32_t vj = L.ev[j];
+                        const uint64_t fj = L.em[j];
+                        const uint64_t cnt_v = ((fj >> lane) & 1ull) ? sig[(size_t)vj * 64 + lane] : 0ull;
+                        finish_entry(a, sig, vj, fj, hacc[(size_t)h * 64 + lane], cnt_v, my_src, L.ed[j], reached,
                                      examined, entries, visits);
                     }
                     __syncthreads();
@@ -608,7 +623,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     aborted = true;
                     break;
                 }
-                for (uint32_t i = lo_n + gtid; i < hi_n; i += gthreads) nxt[lv[i]] = 0ull;
+                for (uint32_t i = lo_n + gtid; i < hi_n; i += gthreads) mk.nxt(lv[i]) = 0ull;
             }
         }
         if (aborted) break;
@@ -623,10 +638,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             const uint32_t v = lv[i];
             const uint64_t m = lm[i];
             if ((m >> lane) & 1ull) sig[(size_t)v * 64 + lane] = 0ull;
-            if (lane == 0) {
-                seen[v] = 0ull;
-                nxt[v] = 0ull;
-            }
+            if (lane == 0) mk.clear(v);
         }
         // sources this kernel did not finish go to the per-source kernel
         if (leader && tid == 0) {
@@ -791,7 +803,7 @@ struct MsbPool {
     uint32_t n = 0, cap = 0, max_levels = 0, hub_rows = 0;
     uint64_t mask_stride = 0, sig_stride = 0;
     TeamCtl* ctl = nullptr;
-    uint64_t *seen = nullptr, *nxt = nullptr, *sig = nullptr, *lst_m = nullptr;
+    uint64_t *masks = nullptr, *sig = nullptr, *lst_m = nullptr;
     double* hacc = nullptr;
     uint32_t *lst_v = nullptr, *lvl = nullptr;
     uint32_t* plan = nullptr;       // [plan_cap]
@@ -807,7 +819,7 @@ size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels) {
 }
 
 void msb_pool_free(MsbPool& p) {
-    for (void* q : {(void*)p.ctl, (void*)p.seen, (void*)p.nxt, (void*)p.sig, (void*)p.lst_m, (void*)p.hacc,
+    for (void* q : {(void*)p.ctl, (void*)p.masks, (void*)p.sig, (void*)p.lst_m, (void*)p.hacc,
                     (void*)p.lst_v, (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small, (void*)p.bhist})
         if (q) (void)hipFree(q);
     p = MsbPool{};
@@ -827,7 +839,7 @@ void msb_pool_discard(MsbPool* p) {
 
 static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t cap, uint32_t max_levels,
                             uint32_t hub_rows, uint32_t plan_cap, hipStream_t st) {
-    if (p.seen && p.n == n && p.teams >= teams && p.wgs >= wgs && p.cap >= cap && p.max_levels >= max_levels &&
+    if (p.masks && p.n == n && p.teams >= teams && p.wgs >= wgs && p.cap >= cap && p.max_levels >= max_levels &&
         p.hub_rows >= hub_rows && p.plan_cap >= plan_cap)
         return;
     BC_HIP_TRY(hipStreamSynchronize(st));
@@ -839,11 +851,10 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     p.max_levels = max_levels;
     p.hub_rows = hub_rows;
     p.plan_cap = std::max<uint32_t>(plan_cap, 1);
-    p.mask_stride = (uint64_t)n + kStaggerWords / 8;
+    p.mask_stride = 2 * (uint64_t)n + kStaggerWords / 4;   // even: records stay 16-byte aligned
     p.sig_stride = (uint64_t)n * 64 + kStaggerWords;
     BC_HIP_TRY(hipMalloc((void**)&p.ctl, (size_t)teams * sizeof(TeamCtl)));
-    BC_HIP_TRY(hipMalloc((void**)&p.seen, (size_t)teams * p.mask_stride * 8));
-    BC_HIP_TRY(hipMalloc((void**)&p.nxt, (size_t)teams * p.mask_stride * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.masks, (size_t)teams * p.mask_stride * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.sig, (size_t)teams * p.sig_stride * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.hacc, (size_t)wgs * hub_rows * 512));
     BC_HIP_TRY(hipMalloc((void**)&p.lst_v, (size_t)teams * cap * 4));
@@ -855,8 +866,7 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     BC_HIP_TRY(hipMalloc((void**)&p.bhist, (size_t)(kPlanBuckets + 1) * 4));
     const size_t words = (size_t)teams * p.mask_stride;
     const unsigned g1 = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.seen, words);
-    hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.nxt, words);
+    hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.masks, words);
     const size_t swords = (size_t)teams * p.sig_stride;
     const unsigned g2 = (unsigned)std::min<size_t>((swords + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u64, dim3(g2), dim3(256), 0, st, p.sig, swords);
@@ -935,8 +945,7 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.retry_count = retry_count;
     a.stats = stats;
     a.ctl = p.ctl;
-    a.seen = p.seen;
-    a.nxt = p.nxt;
+    a.masks = p.masks;
     a.sig = p.sig;
     a.hacc = p.hacc;
     a.lst_v = p.lst_v;
