@@ -86,6 +86,7 @@ namespace {
 
 constexpr double kSafeSigma = 1.8e19;      // below 2^64 = 1.8447e19
 constexpr uint32_t kSpinLimit = 1u << 22;  // barrier polls (about 1 us each) before a team gives up
+constexpr int kPsiLoads = 16;               // backward: psi loads issued back to back
 
 __device__ __forceinline__ unsigned lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -130,6 +131,12 @@ template <class T>
 __device__ __forceinline__ T ld_acq(T* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
+// a team's control words after a team barrier: the barrier orders them, the load only has
+// to be coherent (an acquire load would also invalidate the L2)
+template <class T>
+__device__ __forceinline__ T ld_team(T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 template <class T>
 __device__ __forceinline__ void st_rel(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -165,9 +172,14 @@ struct MsbLds {
 
 // Team-wide barrier over the workgroups of one team, with a bounded wait.  Makes every
 // member's global writes visible to every member.  Returns false if the team has given up.
+// A team of one workgroup needs workgroup scope only; agent scope would write back and
+// invalidate the whole L2 of the XCD at every barrier.
 template <int WG>
 __device__ bool team_sync(MsbLds<WG>& L, TeamCtl* c, uint32_t W, CallStats* stats) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (W > 1)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    else
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (W > 1 && threadIdx.x == 0) {
         uint32_t ok = 1;
@@ -194,7 +206,10 @@ __device__ bool team_sync(MsbLds<WG>& L, TeamCtl* c, uint32_t W, CallStats* stat
         L.ok = 1;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (W > 1)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    else
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     return L.ok != 0u;
 }
 
@@ -272,55 +287,84 @@ __device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, 
     return sdeg;
 }
 
-// forward work unit: up to 64 out-edges [e0, e1) of the level-d entry (v, f)
-template <int WG>
-__device__ __forceinline__ void fwd_unit(const MsbArgs& a, MsbLds<WG>& L, const Masks mk, uint64_t* sig, uint32_t v, uint64_t f, uint32_t e0, uint32_t e1, bool safe) {
+// row updates of one forward unit, lane per source: sig[w][s] += sv for every DAG edge (v, w)
+// of the unit and s in its mask; the edges are taken from the ballot in lane order, their
+// successor and mask read from that lane's registers.  No value is returned: no wait.
+__device__ __forceinline__ void rows_add(uint64_t* sig, uint32_t w, uint64_t dag, uint64_t sv) {
     const unsigned lane = lane_id();
-    const bool act = (f >> lane) & 1ull;
-    const uint32_t e = e0 + lane;
-    const bool ok = e < e1;
-    // independent loads first: this vertex's counts and the unit's successors
-    const uint64_t sv = act ? sig[(size_t)v * 64 + lane] : 0ull;
-    const uint32_t w = ok ? a.col[e] : 0u;
-    uint64_t dag = 0;
-    if (ok) {
-        const ulonglong2 q = mk.both(w);
-        dag = f & ~q.x;
-        // bits only get set during a level, so a plain read that already shows every bit of
-        // dag (stale reads show fewer) proves the OR would change nothing: skip it
-        if ((dag & ~q.y) != 0ull)   // no short-circuit: keeps the record one 16-byte load
-            __hip_atomic_fetch_or((unsigned long long*)&mk.nxt(w), (unsigned long long)dag, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const uint64_t mx = wave_max64(sv);
-    if (lane == 0 && mx > L.maxsig) atomicMax((unsigned long long*)&L.maxsig, (unsigned long long)mx);
-    // phase B, lane per source: one row update per DAG edge of the unit, the edges taken from
-    // the ballot in lane order (their successor and mask read from that lane's registers)
     uint64_t bal = __ballot(dag != 0ull);
-    // two separate loops: the returning form waits for every old value, the other does not
+    while (bal) {
+        const int k = __builtin_ctzll(bal);
+        bal &= bal - 1ull;
+        const uint32_t wj = readlane_u32(w, k);
+        const uint64_t dj = readlane_u64(dag, k);
+        if ((dj >> lane) & 1ull)
+            __hip_atomic_fetch_add((unsigned long long*)&sig[(size_t)wj * 64 + lane], (unsigned long long)sv,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// the same with the old values checked: true if a count of this lane's source carried
+__device__ __forceinline__ bool rows_add_checked(uint64_t* sig, uint32_t w, uint64_t dag, uint64_t sv) {
+    const unsigned lane = lane_id();
+    bool carry = false;
+    uint64_t bal = __ballot(dag != 0ull);
+    while (bal) {
+        const int k = __builtin_ctzll(bal);
+        bal &= bal - 1ull;
+        const uint32_t wj = readlane_u32(w, k);
+        const uint64_t dj = readlane_u64(dag, k);
+        if ((dj >> lane) & 1ull) {
+            const unsigned long long old = atomicAdd((unsigned long long*)&sig[(size_t)wj * 64 + lane],
+                                                     (unsigned long long)sv);
+            carry |= old + sv < old;
+        }
+    }
+    return carry;
+}
+
+// Forward work of one wavefront: two units, A = out-edges [e0A, e1A) of the level-d entry
+// (vA, fA) and B likewise (e0B == e1B: none).  Each unit tests up to 64 edges at once; every
+// load of both units is issued before the first dependent use, so their round trips overlap.
+template <int WG>
+__device__ __forceinline__ void fwd_units(const MsbArgs& a, MsbLds<WG>& L, const Masks mk, uint64_t* sig,
+                                          uint32_t vA, uint64_t fA, uint32_t e0A, uint32_t e1A, uint32_t vB,
+                                          uint64_t fB, uint32_t e0B, uint32_t e1B, bool safe) {
+    const unsigned lane = lane_id();
+    const uint32_t eA = e0A + lane, eB = e0B + lane;
+    const bool okA = eA < e1A, okB = eB < e1B;
+    const bool actA = (fA >> lane) & 1ull, actB = (fB >> lane) & 1ull;
+    // Every load is issued by every lane, idle lanes repeating an address of an active lane
+    // (no extra sectors): loads without branches around them keep the wait counts exact, so
+    // the second unit's gathers do not wait for the first unit's.  An empty unit B (fB = 0,
+    // e0B = e1B) reads vertex 0's row and edge 0, which exist whenever a unit does.
+    const uint32_t lA = actA ? lane : (uint32_t)__builtin_ctzll(fA | (1ull << 63));
+    const uint32_t lB = actB ? lane : (uint32_t)__builtin_ctzll(fB | (1ull << 63));
+    const uint64_t sA = sig[(size_t)vA * 64 + lA];
+    const uint64_t sB = sig[(size_t)vB * 64 + lB];
+    const uint32_t wA = a.col[okA ? eA : e1A - 1];
+    const uint32_t wB = a.col[okB ? eB : (e1B > e0B ? e1B - 1 : 0u)];
+    __builtin_amdgcn_sched_barrier(0);   // the four independent loads above go out first
+    const ulonglong2 qA = mk.both(wA);
+    const ulonglong2 qB = mk.both(wB);
+    const uint64_t svA = actA ? sA : 0ull, svB = actB ? sB : 0ull;
+    const uint64_t dagA = okA ? (fA & ~qA.x) : 0ull, dagB = okB ? (fB & ~qB.x) : 0ull;
+    // bits only get set during a level, so a plain read that already shows every bit of dag
+    // (stale reads show fewer) proves the OR would change nothing: skip it
+    if ((dagA & ~qA.y) != 0ull)
+        __hip_atomic_fetch_or((unsigned long long*)&mk.nxt(wA), (unsigned long long)dagA, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+    if ((dagB & ~qB.y) != 0ull)
+        __hip_atomic_fetch_or((unsigned long long*)&mk.nxt(wB), (unsigned long long)dagB, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t mx = wave_max64(svA > svB ? svA : svB);
+    if (lane == 0 && mx > L.maxsig) atomicMax((unsigned long long*)&L.maxsig, (unsigned long long)mx);
+    // two separate paths: the checked form waits for every old value, the other does not
     if (safe) {
-        while (bal) {
-            const int k = __builtin_ctzll(bal);
-            bal &= bal - 1ull;
-            const uint32_t wj = readlane_u32(w, k);
-            const uint64_t dj = readlane_u64(dag, k);
-            if ((dj >> lane) & 1ull)
-                __hip_atomic_fetch_add((unsigned long long*)&sig[(size_t)wj * 64 + lane], (unsigned long long)sv,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        rows_add(sig, wA, dagA, svA);
+        rows_add(sig, wB, dagB, svB);
     } else {
-        bool carry = false;
-        while (bal) {
-            const int k = __builtin_ctzll(bal);
-            bal &= bal - 1ull;
-            const uint32_t wj = readlane_u32(w, k);
-            const uint64_t dj = readlane_u64(dag, k);
-            if ((dj >> lane) & 1ull) {
-                const unsigned long long old = atomicAdd((unsigned long long*)&sig[(size_t)wj * 64 + lane],
-                                                         (unsigned long long)sv);
-                carry |= old + sv < old;
-            }
-        }
+        const bool carry = rows_add_checked(sig, wA, dagA, svA) | rows_add_checked(sig, wB, dagB, svB);
         const uint64_t cm = __ballot(carry);
         if (lane == 0 && cm) atomicOr((unsigned long long*)&L.ovf, (unsigned long long)cm);
     }
@@ -417,7 +461,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             ctl->maxsig[0] = ctl->maxsig[1] = 0;
         }
         if (!team_sync(L, ctl, W, a.stats)) break;
-        const uint32_t b = ld_acq(&ctl->batch);
+        const uint32_t b = ld_team(&ctl->batch);
         if (b >= nbatch) break;
         const uint32_t base = b * 64;
         const uint32_t nl = min(64u, total - base);
@@ -451,20 +495,20 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 aborted = true;
                 break;
             }
-            const uint32_t hi = ld_acq(&ctl->tail);
+            const uint32_t hi = ld_team(&ctl->tail);
             if (leader && tid == 0) {
                 lvl[d] = lo;
                 lvl[d + 1] = hi;
             }
             if (hi == lo) break;   // level d is empty: the sweep is over (levels 0..d-1)
             const uint64_t room = (uint64_t)a.cap - hi;
-            if (d + 2 > a.max_levels || room < min<uint64_t>(n, ld_acq(&ctl->sdeg[d & 1]))) {
+            if (d + 2 > a.max_levels || room < min<uint64_t>(n, ld_team(&ctl->sdeg[d & 1]))) {
                 stopped = true;
                 d += 1;
                 break;
             }
             // no carry is possible this level if (max count on level d-1) * maxin^2 < 2^64
-            const bool safe = d == 0 || (double)ld_acq(&ctl->maxsig[(d + 1) & 1]) * a.in2 < kSafeSigma;
+            const bool safe = d == 0 || (double)ld_team(&ctl->maxsig[(d + 1) & 1]) * a.in2 < kSafeSigma;
             for (;;) {
                 const uint32_t ch = claim_chunk(L, ctl);
                 const uint32_t c0 = lo + ch * WG;
@@ -486,11 +530,21 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 L.eb[tid] = beg;
                 L.ed[tid] = deg;
                 __syncthreads();
-                for (uint32_t u = wave; u < units; u += NW) {
+                for (uint32_t u = wave; u < units; u += 2 * NW) {   // units u and u + NW
                     const uint32_t j = find_owner<WG>(L.off, u);
                     const uint32_t e0 = L.eb[j] + (u - L.off[j]) * 64;
                     const uint32_t e1 = min(L.eb[j] + L.ed[j], e0 + 64);
-                    fwd_unit<WG>(a, L, mk, sig, L.ev[j], L.em[j], e0, e1, safe);
+                    const uint32_t u2 = u + NW;
+                    uint32_t v2 = 0, e02 = 0, e12 = 0;
+                    uint64_t f2 = 0;
+                    if (u2 < units) {
+                        const uint32_t j2 = find_owner<WG>(L.off, u2);
+                        v2 = L.ev[j2];
+                        f2 = L.em[j2];
+                        e02 = L.eb[j2] + (u2 - L.off[j2]) * 64;
+                        e12 = min(L.eb[j2] + L.ed[j2], e02 + 64);
+                    }
+                    fwd_units<WG>(a, L, mk, sig, L.ev[j], L.em[j], e0, e1, v2, f2, e02, e12, safe);
                 }
                 __syncthreads();
             }
@@ -510,8 +564,8 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             t_phase = t;
         }
         const uint32_t nlev = d;            // levels 0..nlev-1 hold entries
-        const uint32_t n_entries = ld_acq(&ctl->tail);
-        const uint64_t ovf = stopped ? lanes : (ld_acq(&ctl->ovf) & lanes);
+        const uint32_t n_entries = ld_team(&ctl->tail);
+        const uint64_t ovf = stopped ? lanes : (ld_team(&ctl->ovf) & lanes);
         // ---------------- backward sweep ----------------
         if (!stopped) {
             if (leader && tid == 0) lvl[nlev + 1] = lvl[nlev];
@@ -556,7 +610,8 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     L.eb[tid] = beg;
                     L.ed[tid] = deg;
                     L.eh[tid] = row;
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    // the accumulator rows belong to this workgroup alone: workgroup scope
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     __syncthreads();
                     for (uint32_t u = wave; u < units; u += NW) {
                         const uint32_t j = find_owner<WG>(L.off, u);
@@ -578,13 +633,13 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                         }
                         dagc += (uint32_t)__builtin_popcountll(sm);
                         // lane per source: sum psi over the unit's successors, taken from the
-                        // ballot eight at a time so that eight loads are in flight
+                        // ballot kPsiLoads at a time so that as many loads are in flight
                         uint64_t rem = __ballot(sm != 0ull);
                         double acc = 0.0;
                         while (rem) {
-                            double x[8];
+                            double x[kPsiLoads];
 #pragma unroll
-                            for (int t = 0; t < 8; ++t) {
+                            for (int t = 0; t < kPsiLoads; ++t) {
                                 x[t] = 0.0;
                                 if (rem) {
                                     const int k = __builtin_ctzll(rem);
@@ -595,7 +650,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                                 }
                             }
 #pragma unroll
-                            for (int t = 0; t < 8; ++t) acc += x[t];
+                            for (int t = 0; t < kPsiLoads; ++t) acc += x[t];
                         }
                         if (hr < 0) {
                             finish_entry(a, sig, vj, fj, acc, cnt_v, my_src, dj, reached, examined, entries, visits);
@@ -603,9 +658,9 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                             unsafeAtomicAdd(&hacc[(size_t)hr * 64 + lane], acc);
                         }
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     __syncthreads();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                     const uint32_t nh = L.nhub;
                     for (uint32_t h = wave; h < nh; h += NW) {
                         const uint32_t j = L.hub_ent[h];

@@ -186,6 +186,21 @@ def test_batched_teams(bc, team):
     g.free()
 
 
+@pytest.mark.parametrize("team", [1, 2])
+def test_batched_state_reuse(bc, team):
+    """Four state slots for 64 batches: every team runs sixteen batches one after another on
+    the same device state, which each batch must leave clean for the next."""
+    n, u, v = gg.rmat(12, 16, 6)
+    want, ovf, st = oracle_exact("rmat12_16_6", n, u, v)
+    say("batched reuse team", team)
+    g = bc.bc_build_csr(n, u, v)
+    got, info = bc.bc_exact(g, tuning=force(bc, "batched", wgs_per_source=team, sources_per_launch=4), info=True)
+    assert info["path"] == 2 and info["n_sources"] == n
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    rel_close(np_of(got), want, what=f"reuse team={team}")
+    g.free()
+
+
 def test_relabelled_graph_every_path(bc):
     """Graphs from 16,384 vertices run on an internally renumbered copy; every output must
     still come back in the caller's vertex ids."""
