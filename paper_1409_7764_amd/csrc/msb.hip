@@ -127,10 +127,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     }
     return x;
 }
-template <class T>
-__device__ __forceinline__ T ld_acq(T* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 // a team's control words after a team barrier: the barrier orders them, the load only has
 // to be coherent (an acquire load would also invalidate the L2)
 template <class T>
@@ -172,44 +168,43 @@ struct MsbLds {
 
 // Team-wide barrier over the workgroups of one team, with a bounded wait.  Makes every
 // member's global writes visible to every member.  Returns false if the team has given up.
-// A team of one workgroup needs workgroup scope only; agent scope would write back and
-// invalidate the whole L2 of the XCD at every barrier.
+// Each workgroup first gathers its own writes with a workgroup-scope barrier; only thread 0
+// then synchronises at agent scope (one L2 write-back on arrival, one invalidate after the
+// wait; the wait itself polls with plain coherent loads).  A team of one workgroup needs
+// workgroup scope only.
 template <int WG>
 __device__ bool team_sync(MsbLds<WG>& L, TeamCtl* c, uint32_t W, CallStats* stats) {
-    if (W > 1)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    else
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
-    if (W > 1 && threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
         uint32_t ok = 1;
-        const uint32_t gen = ld_acq(&c->bar_gen);
-        const uint32_t arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == W - 1) {
-            __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            uint32_t spins = 0;
-            while (ld_acq(&c->bar_gen) == gen) {
-                if (ld_acq(&c->abort) || ++spins > kSpinLimit) {
-                    st_rel(&c->abort, 1u);
-                    ok = 0;
-                    break;
+        if (W > 1) {
+            const uint32_t gen = ld_team(&c->bar_gen);
+            // acquire-release: publishes this workgroup's writes, and the last arriver takes
+            // every member's before it opens the barrier
+            const uint32_t arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (arrived == W - 1) {
+                __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                uint32_t spins = 0;
+                while (ld_team(&c->bar_gen) == gen) {
+                    if (ld_team(&c->abort) || ++spins > kSpinLimit) {
+                        st_rel(&c->abort, 1u);
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
                 }
-                __builtin_amdgcn_s_sleep(2);
             }
+            if (ld_team(&c->abort)) ok = 0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        if (ld_acq(&c->abort)) ok = 0;
         if (!ok) atomicOr(&stats->pad[0], 1u);
         L.ok = ok;
-    } else if (threadIdx.x == 0) {
-        L.ok = 1;
     }
     __syncthreads();
-    if (W > 1)
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    else
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     return L.ok != 0u;
 }
 
