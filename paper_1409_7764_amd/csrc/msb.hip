@@ -18,9 +18,10 @@
 //   atomics, issued without waiting for the old value whenever a bound on sigma proves that
 //   no carry can occur; otherwise the old value is checked and a carry flags that source,
 //   which is then recounted exactly by the per-source kernel in double precision).  No
-//   operation of the expansion waits for a returned value, so a unit costs two dependent
-//   memory round trips.  The level-(d+1) list is then collected by one coalesced pass over
-//   nxt (entries in vertex order), which also folds the masks into seen.
+//   operation of the expansion waits for a returned value, and a wavefront runs two units at
+//   a time, so a pair of units costs two dependent memory round trips.  The level-(d+1) list
+//   is then collected by one coalesced pass over nxt (entries in vertex order), which also
+//   folds the masks into seen.
 // backward, level d, entry (v, f): succ = f & nxt[w] are the sources with w one level down;
 //   lane s sums psi_s(w), then delta_s(v) = sigma_s(v) * sum, psi_s(v) is stored over
 //   sigma_s(v), and sum over s != v of delta_s(v) is added to BC[v].  Each (v, s) has one
@@ -940,9 +941,12 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     int per_cu = msb_occupancy(wg);
     BC_REQUIRE(per_cu >= 1, BC_E_HIP, "batched kernel does not fit on a compute unit");
     const long max_wgs = (long)per_cu * di.cus;
-    // state slots: one per team; the kernel forms min(batches, slots) teams on the device
-    long teams = std::min<long>(batches, max_wgs);
-    if (team_knob > 0) teams = std::min<long>(teams, std::max<long>(1, max_wgs / team_knob));
+    // state slots: one per team; the kernel forms min(batches, slots) teams on the device.
+    // Unless the caller fixes the team size, a team has at least two workgroups: half as many
+    // batches in flight keeps more of their state in the caches, and a barrier of two
+    // workgroups is cheap.
+    const long wmin = team_knob > 0 ? team_knob : 2;
+    long teams = std::min<long>(batches, std::max<long>(1, max_wgs / wmin));
     if (slots_cap > 0) teams = std::min<long>(teams, slots_cap);
     const uint32_t cap = (uint32_t)std::min<uint64_t>((uint64_t)n * 8 + 64, 0xffffffffull);
     const uint32_t max_levels = 1024;
@@ -1008,7 +1012,7 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.max_levels = p.max_levels;
     a.hub_rows = p.hub_rows;
     a.team_size = team_knob > 0 ? (uint32_t)team_knob : 0u;
-    a.pool_teams = (uint32_t)p.teams;
+    a.pool_teams = (uint32_t)std::min<long>(p.teams, teams);   // a reused pool may hold more
     a.in2 = (double)g.max_in_degree * (double)g.max_in_degree;
     void* args[] = {&a};
     // members of a team wait for each other at level boundaries: a cooperative launch
