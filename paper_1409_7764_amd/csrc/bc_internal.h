@@ -100,6 +100,9 @@ struct Graph {
     // vertices with out-edges first (null when not built)
     uint32_t* rank = nullptr;      // n
     uint32_t* order = nullptr;     // n
+    // fewer than half of the vertices with out-edges lie within the ranked levels of the
+    // batching order: a deep graph (lattice-like), run one source per workgroup by default
+    bool deep = false;
     const uint32_t* krow() const { return prow ? prow : row_ptr; }
     const uint32_t* kcol() const { return pcol ? pcol : col; }
     uint32_t max_out_degree = 0;

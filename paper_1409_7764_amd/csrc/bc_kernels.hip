@@ -867,11 +867,15 @@ static void retry_launch(void* ctx, const uint32_t* list, const uint32_t* count,
 
 int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g);
 
+// Automatic choice: the batched kernel for graphs beyond the LDS path with at least one full
+// batch of sources, unless the graph is deep (most of it lies beyond the batching order's
+// ranked levels): a batch then runs past the kernel's level cap and goes to the per-source
+// kernel anyway.
 static bool want_batched(const Knobs& k, const Graph& g, uint32_t items) {
     if (k.batched < 0) return false;
     const bool lds_ok = k.lds_max_n > 0 && g.n <= k.lds_max_n;
     if (k.batched > 0) return true;
-    return !lds_ok && items >= 64;
+    return !lds_ok && items >= 64 && !g.deep;
 }
 
 int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {

@@ -426,6 +426,7 @@ static void build_order(Graph& g, int vbits, hipStream_t st) {
         placed += nl;
         nf = nl;
     }
+    g.deep = (uint64_t)placed * 2 < (uint64_t)(n - g.zero_out_degree);
     if (placed < n) {
         uint32_t* c = cnt + 2 + kOrderLevels + 1;
         BC_HIP_TRY(hipMemsetAsync(c, 0, sizeof(uint32_t), st));
@@ -562,11 +563,11 @@ void build_csr_device(int32_t n, int64_t m_in, const uint32_t* d_src, const uint
     BC_HIP_TRY(hipFreeAsync(counters, st));
     BC_HIP_TRY(hipStreamSynchronize(st));
     g.m = m;
-    build_order(g, vbits, st);
-    BC_HIP_TRY(hipStreamSynchronize(st));
     g.max_out_degree = h[3];
     g.max_in_degree = h[2];
     g.zero_out_degree = h[1];
+    build_order(g, vbits, st);
+    BC_HIP_TRY(hipStreamSynchronize(st));
 }
 
 }  // namespace bcmi
