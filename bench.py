@@ -33,18 +33,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(info):
+def algorithmic_bytes(info, n):
     """Bytes the launch's design must move, from its exact work counters.
 
     One source per workgroup (paths 0, 1): 96 B per reached vertex, 16 B per examined edge,
     24 B per shortest-path DAG edge, summed over sources.
-    64-source batches (path 2): 168 B per level-list entry, 24 B per out-edge read for an
-    entry (forward + backward), 32 B per reached (vertex, source) pair, 24 B per DAG
-    (edge, source) pair.
+    64-source batches (path 2): 144 B per level-list entry, 24 B per out-edge read for an
+    entry (forward + backward), 20 B per reached (vertex, source) pair (32-bit count read in
+    each sweep and cleared, psi written), 16 B per DAG (edge, source) pair (32-bit count
+    atomic, psi read), and 16 B per vertex for every level-collect pass.
     """
     if info["path"] == 2:
-        return (168 * info["batch_entries"] + 24 * info["batch_edge_visits"] + 32 * info["reached"]
-                + 24 * info["dag_edges"])
+        return (144 * info["batch_entries"] + 24 * info["batch_edge_visits"] + 20 * info["reached"]
+                + 16 * info["dag_edges"] + 16 * n * info["batch_scans"])
     return 96 * info["reached"] + 16 * info["examined"] + 24 * info["dag_edges"]
 
 
@@ -163,7 +164,7 @@ def bench_single(args, torch, bcmi, gg):
     k = len(sources)
     kernel_ms = float(np.mean([i["kernel_ms"] for i in infos]))
     inf = infos[-1]
-    nbytes = algorithmic_bytes(inf)
+    nbytes = algorithmic_bytes(inf, n)
     achieved = nbytes / (kernel_ms / 1e3) / 1e9
     traffic = load_traffic(cfg["workload"], 1)
     res = {
@@ -173,7 +174,7 @@ def bench_single(args, torch, bcmi, gg):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64+f64",
+        "dtype": "u32+f64" if inf["path"] == 2 else "u64+f64",
         "data": "synthetic",
         "config": cfg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -188,6 +189,11 @@ def bench_single(args, torch, bcmi, gg):
             "sigma_fp64_fallback_sources": inf["n_sigma_fp64_fallback"],
             "path": ["global", "lds", "batched"][inf["path"]], "tuning": tune,
             "batch_entries": inf["batch_entries"], "batch_edge_visits": inf["batch_edge_visits"],
+            "batch_scans": inf["batch_scans"],
+            # the per-source accounting 16|E_s| + 32|D_s| + 92|R_s| summed over sources, whatever
+            # the path: what one source at a time would move (batches share their edge reads)
+            "per_source_convention_gbs": (16 * inf["examined"] + 32 * inf["dag_edges"] + 92 * inf["reached"])
+            / (kernel_ms / 1e3) / 1e9,
             "batch_cycles_fwd_bwd_reset": inf["batch_cycles"],
             "kernel_ms_all": [i["kernel_ms"] for i in infos],
         },

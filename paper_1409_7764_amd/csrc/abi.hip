@@ -130,6 +130,7 @@ static void fill_info(Graph& g, hipStream_t st, int path, double ms, uint32_t ex
     out.dag_edges = cs.dag_edges;
     out.batch_entries = cs.entries;
     out.batch_edge_visits = cs.edge_visits;
+    out.batch_scans = cs.scans;
     for (int i = 0; i < 3; ++i) out.batch_cycles[i] = cs.cycles[i];
     *info = out;
 }

@@ -66,6 +66,7 @@ struct CallStats {
     uint64_t dag_edges;      // sum over sources of shortest-path DAG edges
     uint64_t entries;        // batched path: (vertex, level) entries of the batches' level lists
     uint64_t edge_visits;    // batched path: out-edges read per entry (once per sweep)
+    uint64_t scans;          // batched path: level-collect passes over all vertices
     uint64_t cycles[3];      // batched path: workgroup clock cycles in forward, backward, reset
 };
 

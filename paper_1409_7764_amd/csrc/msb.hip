@@ -9,22 +9,24 @@
 //   nxt[v]      sources reaching v at level d+1 (forward); the level-(d+1) masks, scattered,
 //               during the backward sweep
 //               (seen and nxt of a vertex share one 16-byte record: one gather per edge)
-//   sig[v][s]   shortest-path count sigma_s(v) (uint64); after v's level has been finished
-//               in the backward sweep, psi_s(v) = (1 + delta_s(v)) / sigma_s(v) (double bits)
+//   sig[v][s]   shortest-path count sigma_s(v) (uint32: a 256-byte row)
+//   psi[v][s]   psi_s(v) = (1 + delta_s(v)) / sigma_s(v) (double), written when the backward
+//               sweep finishes v's level
 //
 // forward, level d, entry (v, f): for each successor w the lanes of one wavefront test 64
 //   edges at once: dag = f & ~seen[w] are the sources with w at level d+1; they are OR-ed
-//   into nxt[w] and, lane per source, sig[w][s] += sig[v][s] for s in dag (64-bit integer
-//   atomics, issued without waiting for the old value whenever a bound on sigma proves that
-//   no carry can occur; otherwise the old value is checked and a carry flags that source,
-//   which is then recounted exactly by the per-source kernel in double precision).  No
-//   operation of the expansion waits for a returned value, and a wavefront runs two units at
+//   into nxt[w] and, lane per source, sig[w][s] += sig[v][s] for s in dag (32-bit integer
+//   atomics, never waiting for the old value).  sigma_s(w) is at most in-degree(w) times the
+//   largest sigma_s on level d, so a lane whose sigma_s(v) times the largest in-degree reaches
+//   2^32 is flagged before its sums can wrap; the per-source kernel recounts that source
+//   (64-bit counts, then double precision).  No operation of the expansion waits for a
+//   returned value, and a wavefront runs two units at
 //   a time, so a pair of units costs two dependent memory round trips.  The level-(d+1) list
 //   is then collected by one coalesced pass over nxt (entries in vertex order), which also
 //   folds the masks into seen.
 // backward, level d, entry (v, f): succ = f & nxt[w] are the sources with w one level down;
-//   lane s sums psi_s(w), then delta_s(v) = sigma_s(v) * sum, psi_s(v) is stored over
-//   sigma_s(v), and sum over s != v of delta_s(v) is added to BC[v].  Each (v, s) has one
+//   lane s sums psi_s(w), then delta_s(v) = sigma_s(v) * sum, psi_s(v) is stored, and sum
+//   over s != v of delta_s(v) is added to BC[v].  Each (v, s) has one
 //   owner lane: no atomics on delta.  A vertex with more than 64 out-edges is split into
 //   pieces; their partial sums meet in a per-batch accumulator row before the owner
 //   finishes the vertex.
@@ -50,7 +52,6 @@ struct alignas(128) TeamCtl {
     uint32_t cc;             // chunk claim counter of the current phase
     uint32_t abort;          // a barrier wait ran out: every member leaves
     uint32_t sdeg[2];        // out-degree sum of a level (double-buffered by level parity)
-    uint64_t maxsig[2];      // largest count met while expanding a level (by parity)
     uint64_t ovf;            // sources whose counts carried out of 64 bits
     uint32_t pad[16];
 };
@@ -67,7 +68,8 @@ struct MsbArgs {
     CallStats* stats;
     TeamCtl* ctl;                // [teams]
     uint64_t* masks;             // [teams][n][2]: {seen, nxt} per vertex
-    uint64_t* sig;               // [teams][n][64]
+    uint32_t* sig;               // [teams][n][64] counts
+    double* psi;                 // [teams][n][64]
     double* hacc;                // [workgroups][hub_rows][64]
     uint32_t* lst_v;             // [teams][cap]
     uint64_t* lst_m;             // [teams][cap]
@@ -75,17 +77,17 @@ struct MsbArgs {
     int32_t n;
     uint64_t mask_stride;        // elements between two teams' mask arrays
     uint64_t sig_stride;         // elements between two teams' count rows
+    uint64_t psi_stride;         // elements between two teams' psi rows
     uint32_t cap;
     uint32_t max_levels;
     uint32_t hub_rows;
     uint32_t team_size;          // workgroups per team; 0 = as many as the batch count allows
     uint32_t pool_teams;         // team slots in the pool
-    double in2;                  // (largest in-degree)^2
+    uint32_t sig_cap;            // largest count c with c * (largest in-degree) < 2^32
 };
 
 namespace {
 
-constexpr double kSafeSigma = 1.8e19;      // below 2^64 = 1.8447e19
 constexpr uint32_t kSpinLimit = 1u << 22;  // barrier polls (about 1 us each) before a team gives up
 constexpr int kPsiLoads = 16;               // backward: psi loads issued back to back
 
@@ -98,16 +100,6 @@ __device__ __forceinline__ uint32_t readlane_u32(uint32_t x, int k) {
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int k) {
     const uint32_t lo = readlane_u32((uint32_t)x, k), hi = readlane_u32((uint32_t)(x >> 32), k);
     return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ double u2d(uint64_t x) { return __longlong_as_double((long long)x); }
-__device__ __forceinline__ uint64_t d2u(double x) { return (uint64_t)__double_as_longlong(x); }
-__device__ __forceinline__ uint64_t wave_max64(uint64_t x) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        const uint64_t y = (uint64_t)__shfl_xor((long long)x, d, 64);
-        x = x > y ? x : y;
-    }
-    return x;
 }
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -163,8 +155,7 @@ struct MsbLds {
     uint32_t nhub;
     uint32_t chunk;
     uint32_t ok;            // 0 once the team gave up on a barrier
-    uint64_t ovf;           // this workgroup's carries, flushed to the team at level ends
-    uint64_t maxsig;        // this workgroup's largest count on the current level
+    uint64_t ovf;           // sources flagged by this workgroup, flushed to the team at level ends
 };
 
 // Team-wide barrier over the workgroups of one team, with a bounded wait.  Makes every
@@ -286,7 +277,7 @@ __device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, 
 // row updates of one forward unit, lane per source: sig[w][s] += sv for every DAG edge (v, w)
 // of the unit and s in its mask; the edges are taken from the ballot in lane order, their
 // successor and mask read from that lane's registers.  No value is returned: no wait.
-__device__ __forceinline__ void rows_add(uint64_t* sig, uint32_t w, uint64_t dag, uint64_t sv) {
+__device__ __forceinline__ void rows_add(uint32_t* sig, uint32_t w, uint64_t dag, uint32_t sv) {
     const unsigned lane = lane_id();
     uint64_t bal = __ballot(dag != 0ull);
     while (bal) {
@@ -295,37 +286,17 @@ __device__ __forceinline__ void rows_add(uint64_t* sig, uint32_t w, uint64_t dag
         const uint32_t wj = readlane_u32(w, k);
         const uint64_t dj = readlane_u64(dag, k);
         if ((dj >> lane) & 1ull)
-            __hip_atomic_fetch_add((unsigned long long*)&sig[(size_t)wj * 64 + lane], (unsigned long long)sv,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&sig[(size_t)wj * 64 + lane], sv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-}
-
-// the same with the old values checked: true if a count of this lane's source carried
-__device__ __forceinline__ bool rows_add_checked(uint64_t* sig, uint32_t w, uint64_t dag, uint64_t sv) {
-    const unsigned lane = lane_id();
-    bool carry = false;
-    uint64_t bal = __ballot(dag != 0ull);
-    while (bal) {
-        const int k = __builtin_ctzll(bal);
-        bal &= bal - 1ull;
-        const uint32_t wj = readlane_u32(w, k);
-        const uint64_t dj = readlane_u64(dag, k);
-        if ((dj >> lane) & 1ull) {
-            const unsigned long long old = atomicAdd((unsigned long long*)&sig[(size_t)wj * 64 + lane],
-                                                     (unsigned long long)sv);
-            carry |= old + sv < old;
-        }
-    }
-    return carry;
 }
 
 // Forward work of one wavefront: two units, A = out-edges [e0A, e1A) of the level-d entry
 // (vA, fA) and B likewise (e0B == e1B: none).  Each unit tests up to 64 edges at once; every
 // load of both units is issued before the first dependent use, so their round trips overlap.
 template <int WG>
-__device__ __forceinline__ void fwd_units(const MsbArgs& a, MsbLds<WG>& L, const Masks mk, uint64_t* sig,
+__device__ __forceinline__ void fwd_units(const MsbArgs& a, MsbLds<WG>& L, const Masks mk, uint32_t* sig,
                                           uint32_t vA, uint64_t fA, uint32_t e0A, uint32_t e1A, uint32_t vB,
-                                          uint64_t fB, uint32_t e0B, uint32_t e1B, bool safe) {
+                                          uint64_t fB, uint32_t e0B, uint32_t e1B) {
     const unsigned lane = lane_id();
     const uint32_t eA = e0A + lane, eB = e0B + lane;
     const bool okA = eA < e1A, okB = eB < e1B;
@@ -336,14 +307,14 @@ __device__ __forceinline__ void fwd_units(const MsbArgs& a, MsbLds<WG>& L, const
     // e0B = e1B) reads vertex 0's row and edge 0, which exist whenever a unit does.
     const uint32_t lA = actA ? lane : (uint32_t)__builtin_ctzll(fA | (1ull << 63));
     const uint32_t lB = actB ? lane : (uint32_t)__builtin_ctzll(fB | (1ull << 63));
-    const uint64_t sA = sig[(size_t)vA * 64 + lA];
-    const uint64_t sB = sig[(size_t)vB * 64 + lB];
+    const uint32_t sA = sig[(size_t)vA * 64 + lA];
+    const uint32_t sB = sig[(size_t)vB * 64 + lB];
     const uint32_t wA = a.col[okA ? eA : e1A - 1];
     const uint32_t wB = a.col[okB ? eB : (e1B > e0B ? e1B - 1 : 0u)];
     __builtin_amdgcn_sched_barrier(0);   // the four independent loads above go out first
     const ulonglong2 qA = mk.both(wA);
     const ulonglong2 qB = mk.both(wB);
-    const uint64_t svA = actA ? sA : 0ull, svB = actB ? sB : 0ull;
+    const uint32_t svA = actA ? sA : 0u, svB = actB ? sB : 0u;
     const uint64_t dagA = okA ? (fA & ~qA.x) : 0ull, dagB = okB ? (fB & ~qB.x) : 0ull;
     // bits only get set during a level, so a plain read that already shows every bit of dag
     // (stale reads show fewer) proves the OR would change nothing: skip it
@@ -353,30 +324,24 @@ __device__ __forceinline__ void fwd_units(const MsbArgs& a, MsbLds<WG>& L, const
     if ((dagB & ~qB.y) != 0ull)
         __hip_atomic_fetch_or((unsigned long long*)&mk.nxt(wB), (unsigned long long)dagB, __ATOMIC_RELAXED,
                               __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t mx = wave_max64(svA > svB ? svA : svB);
-    if (lane == 0 && mx > L.maxsig) atomicMax((unsigned long long*)&L.maxsig, (unsigned long long)mx);
-    // two separate paths: the checked form waits for every old value, the other does not
-    if (safe) {
-        rows_add(sig, wA, dagA, svA);
-        rows_add(sig, wB, dagB, svB);
-    } else {
-        const bool carry = rows_add_checked(sig, wA, dagA, svA) | rows_add_checked(sig, wB, dagB, svB);
-        const uint64_t cm = __ballot(carry);
-        if (lane == 0 && cm) atomicOr((unsigned long long*)&L.ovf, (unsigned long long)cm);
-    }
+    // a source whose count here could carry its successors' sums past 32 bits is handed on
+    const uint64_t risk = __ballot(svA > a.sig_cap || svB > a.sig_cap);
+    if (lane == 0 && risk) atomicOr((unsigned long long*)&L.ovf, (unsigned long long)risk);
+    rows_add(sig, wA, dagA, svA);
+    rows_add(sig, wB, dagB, svB);
 }
 
 // finishes entry (v, f) of level d with the summed successor psi in `acc`; `count` is this
 // lane's sigma_s(v), read by the caller
-__device__ __forceinline__ void finish_entry(const MsbArgs& a, uint64_t* sig, uint32_t v, uint64_t f, double acc,
-                                             uint64_t count, uint32_t my_src, uint32_t deg, uint32_t& reached,
+__device__ __forceinline__ void finish_entry(const MsbArgs& a, double* psi, uint32_t v, uint64_t f, double acc,
+                                             uint32_t count, uint32_t my_src, uint32_t deg, uint32_t& reached,
                                              uint64_t& examined, uint32_t& entries, uint64_t& visits) {
     const unsigned lane = lane_id();
     double c = 0.0;
     if ((f >> lane) & 1ull) {
         const double sigma = (double)count;
         const double delta = sigma * acc;
-        sig[(size_t)v * 64 + lane] = d2u((1.0 + delta) / sigma);
+        psi[(size_t)v * 64 + lane] = (1.0 + delta) / sigma;
         if (my_src != v) c = delta;
     }
     c = wave_sum(c);
@@ -430,7 +395,8 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     TeamCtl* ctl = a.ctl + team;
     const size_t n = (size_t)a.n;
     const Masks mk{a.masks + (size_t)team * a.mask_stride};
-    uint64_t* sig = a.sig + (size_t)team * a.sig_stride;
+    uint32_t* sig = a.sig + (size_t)team * a.sig_stride;
+    double* psi = a.psi + (size_t)team * a.psi_stride;
     double* hacc = a.hacc + (size_t)blockIdx.x * a.hub_rows * 64;
     uint32_t* lv = a.lst_v + (size_t)team * a.cap;
     uint64_t* lm = a.lst_m + (size_t)team * a.cap;
@@ -439,13 +405,12 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     const uint32_t gwave = member * NW + wave, gwaves = W * NW;
     uint32_t reached = 0, dagc = 0, entries = 0;
     uint64_t examined = 0, visits = 0;
-    uint32_t n_done = 0, levels_max = 0;
+    uint32_t n_done = 0, levels_max = 0, scans = 0;
     uint64_t cyc[3] = {0, 0, 0};   // thread 0: clock cycles in forward, backward, reset
 
     if (tid == 0) {
         L.nhub = 0;
         L.ovf = 0;
-        L.maxsig = 0;
     }
     for (;;) {
         if (leader && tid == 0) {
@@ -454,7 +419,6 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             ctl->cc = 0;
             ctl->ovf = 0;
             ctl->sdeg[0] = ctl->sdeg[1] = 0;
-            ctl->maxsig[0] = ctl->maxsig[1] = 0;
         }
         if (!team_sync(L, ctl, W, a.stats)) break;
         const uint32_t b = ld_team(&ctl->batch);
@@ -466,7 +430,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
         if (leader && wave == 0 && lane < nl) {   // level 0: the sources themselves
             __hip_atomic_fetch_or((unsigned long long*)&mk.nxt(my_src), (unsigned long long)(1ull << lane),
                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sig[(size_t)my_src * 64 + lane] = 1ull;
+            sig[(size_t)my_src * 64 + lane] = 1u;
         }
         // ---------------- forward sweep ----------------
         uint64_t t_phase = clock64();
@@ -480,7 +444,6 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             }
             if (leader && tid == 0) {
                 ctl->cc = 0;                       // chunk counter of this level's expansion
-                ctl->maxsig[d & 1] = 0;            // filled while expanding level d
                 ctl->sdeg[(d + 1) & 1] = 0;        // filled by the next level's scan
             }
             // level d: the vertices some source reached in the previous expansion
@@ -503,8 +466,6 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 d += 1;
                 break;
             }
-            // no carry is possible this level if (max count on level d-1) * maxin^2 < 2^64
-            const bool safe = d == 0 || (double)ld_team(&ctl->maxsig[(d + 1) & 1]) * a.in2 < kSafeSigma;
             for (;;) {
                 const uint32_t ch = claim_chunk(L, ctl);
                 const uint32_t c0 = lo + ch * WG;
@@ -540,14 +501,12 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                         e02 = L.eb[j2] + (u2 - L.off[j2]) * 64;
                         e12 = min(L.eb[j2] + L.ed[j2], e02 + 64);
                     }
-                    fwd_units<WG>(a, L, mk, sig, L.ev[j], L.em[j], e0, e1, v2, f2, e02, e12, safe);
+                    fwd_units<WG>(a, L, mk, sig, L.ev[j], L.em[j], e0, e1, v2, f2, e02, e12);
                 }
                 __syncthreads();
             }
             if (tid == 0) {   // flush this workgroup's level results to the team
-                if (L.maxsig) atomicMax((unsigned long long*)&ctl->maxsig[d & 1], (unsigned long long)L.maxsig);
                 if (L.ovf) atomicOr((unsigned long long*)&ctl->ovf, (unsigned long long)L.ovf);
-                L.maxsig = 0;
                 L.ovf = 0;
             }
             lo = hi;
@@ -619,8 +578,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                         const uint32_t e = e0 + lane;
                         const int32_t hr = L.eh[j];
                         // the entry's own counts, read early when this unit finishes the entry
-                        const uint64_t cnt_v =
-                            (hr < 0 && ((fj >> lane) & 1ull)) ? sig[(size_t)vj * 64 + lane] : 0ull;
+                        const uint32_t cnt_v = (hr < 0 && ((fj >> lane) & 1ull)) ? sig[(size_t)vj * 64 + lane] : 0u;
                         uint32_t w = 0;
                         uint64_t sm = 0;
                         if (e < e1) {
@@ -642,14 +600,14 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                                     rem &= rem - 1ull;
                                     const uint32_t wt = readlane_u32(w, k);
                                     const uint64_t mt = readlane_u64(sm, k);
-                                    if ((mt >> lane) & 1ull) x[t] = u2d(sig[(size_t)wt * 64 + lane]);
+                                    if ((mt >> lane) & 1ull) x[t] = psi[(size_t)wt * 64 + lane];
                                 }
                             }
 #pragma unroll
                             for (int t = 0; t < kPsiLoads; ++t) acc += x[t];
                         }
                         if (hr < 0) {
-                            finish_entry(a, sig, vj, fj, acc, cnt_v, my_src, dj, reached, examined, entries, visits);
+                            finish_entry(a, psi, vj, fj, acc, cnt_v, my_src, dj, reached, examined, entries, visits);
                         } else if (((fj >> lane) & 1ull) && acc != 0.0) {
                             unsafeAtomicAdd(&hacc[(size_t)hr * 64 + lane], acc);
                         }
@@ -662,8 +620,8 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                         const uint32_t j = L.hub_ent[h];
                         const uint32_t vj = L.ev[j];
                         const uint64_t fj = L.em[j];
-                        const uint64_t cnt_v = ((fj >> lane) & 1ull) ? sig[(size_t)vj * 64 + lane] : 0ull;
-                        finish_entry(a, sig, vj, fj, hacc[(size_t)h * 64 + lane], cnt_v, my_src, L.ed[j], reached,
+                        const uint32_t cnt_v = ((fj >> lane) & 1ull) ? sig[(size_t)vj * 64 + lane] : 0u;
+                        finish_entry(a, psi, vj, fj, hacc[(size_t)h * 64 + lane], cnt_v, my_src, L.ed[j], reached,
                                      examined, entries, visits);
                     }
                     __syncthreads();
@@ -688,7 +646,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
         for (uint32_t i = gwave; i < n_entries; i += gwaves) {
             const uint32_t v = lv[i];
             const uint64_t m = lm[i];
-            if ((m >> lane) & 1ull) sig[(size_t)v * 64 + lane] = 0ull;
+            if ((m >> lane) & 1ull) sig[(size_t)v * 64 + lane] = 0u;   // psi is written before it is read
             if (lane == 0) mk.clear(v);
         }
         // sources this kernel did not finish go to the per-source kernel
@@ -705,6 +663,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             }
             n_done += (uint32_t)__builtin_popcountll(lanes & ~ovf);
             if (!stopped) levels_max = max(levels_max, nlev);
+            scans += stopped ? nlev : nlev + 1;   // the last pass found the empty level
         }
         if (!team_sync(L, ctl, W, a.stats)) break;
         cyc[2] += clock64() - t_phase;
@@ -726,6 +685,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     }
     if (tid == 0) {
         if (n_done) atomicAdd(&a.stats->n_done, n_done);
+        if (scans) atomicAdd((unsigned long long*)&a.stats->scans, (unsigned long long)scans);
         if (levels_max) atomicMax(&a.stats->levels_max, levels_max);
         for (int i = 0; i < 3; ++i)
             if (cyc[i]) atomicAdd((unsigned long long*)&a.stats->cycles[i], (unsigned long long)cyc[i]);
@@ -852,9 +812,11 @@ constexpr uint64_t kStaggerWords = 37 * 512;
 struct MsbPool {
     int teams = 0, wgs = 0;
     uint32_t n = 0, cap = 0, max_levels = 0, hub_rows = 0;
-    uint64_t mask_stride = 0, sig_stride = 0;
+    uint64_t mask_stride = 0, sig_stride = 0, psi_stride = 0;
     TeamCtl* ctl = nullptr;
-    uint64_t *masks = nullptr, *sig = nullptr, *lst_m = nullptr;
+    uint64_t *masks = nullptr, *lst_m = nullptr;
+    uint32_t* sig = nullptr;
+    double* psi = nullptr;
     double* hacc = nullptr;
     uint32_t *lst_v = nullptr, *lvl = nullptr;
     uint32_t* plan = nullptr;       // [plan_cap]
@@ -865,12 +827,12 @@ struct MsbPool {
 };
 
 size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels) {
-    return sizeof(TeamCtl) + (size_t)n * (8 + 8 + 512) + 3 * kStaggerWords * 8 + (size_t)cap * 12 +
+    return sizeof(TeamCtl) + (size_t)n * (16 + 256 + 512) + 4 * kStaggerWords * 8 + (size_t)cap * 12 +
            4 * ((size_t)max_levels + 2);
 }
 
 void msb_pool_free(MsbPool& p) {
-    for (void* q : {(void*)p.ctl, (void*)p.masks, (void*)p.sig, (void*)p.lst_m, (void*)p.hacc,
+    for (void* q : {(void*)p.ctl, (void*)p.masks, (void*)p.sig, (void*)p.psi, (void*)p.lst_m, (void*)p.hacc,
                     (void*)p.lst_v, (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small, (void*)p.bhist})
         if (q) (void)hipFree(q);
     p = MsbPool{};
@@ -903,10 +865,12 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     p.hub_rows = hub_rows;
     p.plan_cap = std::max<uint32_t>(plan_cap, 1);
     p.mask_stride = 2 * (uint64_t)n + kStaggerWords / 4;   // even: records stay 16-byte aligned
-    p.sig_stride = (uint64_t)n * 64 + kStaggerWords;
+    p.sig_stride = (uint64_t)n * 64 + 2 * kStaggerWords;
+    p.psi_stride = (uint64_t)n * 64 + kStaggerWords;
     BC_HIP_TRY(hipMalloc((void**)&p.ctl, (size_t)teams * sizeof(TeamCtl)));
     BC_HIP_TRY(hipMalloc((void**)&p.masks, (size_t)teams * p.mask_stride * 8));
-    BC_HIP_TRY(hipMalloc((void**)&p.sig, (size_t)teams * p.sig_stride * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.sig, (size_t)teams * p.sig_stride * 4));
+    BC_HIP_TRY(hipMalloc((void**)&p.psi, (size_t)teams * p.psi_stride * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.hacc, (size_t)wgs * hub_rows * 512));
     BC_HIP_TRY(hipMalloc((void**)&p.lst_v, (size_t)teams * cap * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.lst_m, (size_t)teams * cap * 8));
@@ -918,9 +882,9 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     const size_t words = (size_t)teams * p.mask_stride;
     const unsigned g1 = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.masks, words);
-    const size_t swords = (size_t)teams * p.sig_stride;
+    const size_t swords = (size_t)teams * p.sig_stride / 2;   // counts, as 64-bit words
     const unsigned g2 = (unsigned)std::min<size_t>((swords + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_zero_u64, dim3(g2), dim3(256), 0, st, p.sig, swords);
+    hipLaunchKernelGGL(k_zero_u64, dim3(g2), dim3(256), 0, st, (uint64_t*)p.sig, swords);
     const size_t cw = (size_t)teams * sizeof(TeamCtl) / 8;
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::max<size_t>(1, std::min<size_t>((cw + 255) / 256, 1024))),
                        dim3(256), 0, st, (uint64_t*)p.ctl, cw);
@@ -1001,6 +965,7 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.ctl = p.ctl;
     a.masks = p.masks;
     a.sig = p.sig;
+    a.psi = p.psi;
     a.hacc = p.hacc;
     a.lst_v = p.lst_v;
     a.lst_m = p.lst_m;
@@ -1008,12 +973,13 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.n = g.n;
     a.mask_stride = p.mask_stride;
     a.sig_stride = p.sig_stride;
+    a.psi_stride = p.psi_stride;
     a.cap = p.cap;
     a.max_levels = p.max_levels;
     a.hub_rows = p.hub_rows;
     a.team_size = team_knob > 0 ? (uint32_t)team_knob : 0u;
     a.pool_teams = (uint32_t)std::min<long>(p.teams, teams);   // a reused pool may hold more
-    a.in2 = (double)g.max_in_degree * (double)g.max_in_degree;
+    a.sig_cap = g.max_in_degree ? (uint32_t)(0xffffffffull / g.max_in_degree) : 0xffffffffu;
     void* args[] = {&a};
     // members of a team wait for each other at level boundaries: a cooperative launch
     // guarantees that every workgroup of the grid is resident at once
