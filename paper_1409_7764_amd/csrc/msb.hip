@@ -70,7 +70,8 @@ struct MsbArgs {
     uint64_t* masks;             // [teams][n][2]: {seen, nxt} per vertex
     uint32_t* sig;               // [teams][n][64] counts
     double* psi;                 // [teams][n][64]
-    double* hacc;                // [workgroups][hub_rows][64]
+    double* hacc;                // [workgroups][hub_rows][64], accumulator rows beyond the LDS ones
+    double* bcp;                 // [teams][cap]: each list entry's BC contribution
     uint32_t* lst_v;             // [teams][cap]
     uint64_t* lst_m;             // [teams][cap]
     uint32_t* lvl;               // [teams][max_levels + 2]
@@ -152,6 +153,7 @@ struct MsbLds {
     uint32_t ed[WG];        // out-degree
     int32_t eh[WG];         // accumulator row of a split entry, -1 otherwise
     uint32_t hub_ent[WG];   // accumulator row -> chunk entry
+    double hl[WG / 8][64];  // the first accumulator rows (LDS atomics: no wait on memory)
     uint32_t nhub;
     uint32_t chunk;
     uint32_t ok;            // 0 once the team gave up on a barrier
@@ -331,11 +333,12 @@ __device__ __forceinline__ void fwd_units(const MsbArgs& a, MsbLds<WG>& L, const
     rows_add(sig, wB, dagB, svB);
 }
 
-// finishes entry (v, f) of level d with the summed successor psi in `acc`; `count` is this
-// lane's sigma_s(v), read by the caller
-__device__ __forceinline__ void finish_entry(const MsbArgs& a, double* psi, uint32_t v, uint64_t f, double acc,
-                                             uint32_t count, uint32_t my_src, uint32_t deg, uint32_t& reached,
-                                             uint64_t& examined, uint32_t& entries, uint64_t& visits) {
+// finishes list entry idx = (v, f) of level d with the summed successor psi in `acc`;
+// `count` is this lane's sigma_s(v), read by the caller
+__device__ __forceinline__ void finish_entry(double* psi, double* bcp, uint32_t idx, uint32_t v, uint64_t f,
+                                             double acc, uint32_t count, uint32_t my_src, uint32_t deg,
+                                             uint32_t& reached, uint64_t& examined, uint32_t& entries,
+                                             uint64_t& visits) {
     const unsigned lane = lane_id();
     double c = 0.0;
     if ((f >> lane) & 1ull) {
@@ -346,7 +349,7 @@ __device__ __forceinline__ void finish_entry(const MsbArgs& a, double* psi, uint
     }
     c = wave_sum(c);
     if (lane == 0) {
-        if (c != 0.0) unsafeAtomicAdd(&a.bc[a.iperm ? a.iperm[v] : v], c);
+        bcp[idx] = c;   // added to BC[v] when the batch is reset: no atomic in the sweep
         const uint32_t pc = (uint32_t)__builtin_popcountll(f);
         reached += pc;
         examined += (uint64_t)pc * deg;
@@ -398,6 +401,8 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     uint32_t* sig = a.sig + (size_t)team * a.sig_stride;
     double* psi = a.psi + (size_t)team * a.psi_stride;
     double* hacc = a.hacc + (size_t)blockIdx.x * a.hub_rows * 64;
+    double* bcp = a.bcp + (size_t)team * a.cap;
+    constexpr uint32_t HL = WG / 8;   // accumulator rows in LDS
     uint32_t* lv = a.lst_v + (size_t)team * a.cap;
     uint64_t* lm = a.lst_m + (size_t)team * a.cap;
     uint32_t* lvl = a.lvl + (size_t)team * (a.max_levels + 2);
@@ -555,7 +560,11 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     if (np > 1) {
                         row = (int32_t)atomicAdd(&L.nhub, 1u);
                         L.hub_ent[row] = tid;
-                        for (int q = 0; q < 64; ++q) hacc[(size_t)row * 64 + q] = 0.0;
+                        if ((uint32_t)row < HL) {
+                            for (int q = 0; q < 64; ++q) L.hl[row][q] = 0.0;
+                        } else {
+                            for (int q = 0; q < 64; ++q) hacc[(size_t)(row - HL) * 64 + q] = 0.0;
+                        }
                     }
                     uint32_t units;
                     const uint32_t off = block_excl_scan<WG>(np, units, L.wsum);
@@ -607,9 +616,13 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                             for (int t = 0; t < kPsiLoads; ++t) acc += x[t];
                         }
                         if (hr < 0) {
-                            finish_entry(a, psi, vj, fj, acc, cnt_v, my_src, dj, reached, examined, entries, visits);
+                            finish_entry(psi, bcp, c0 + j, vj, fj, acc, cnt_v, my_src, dj, reached, examined,
+                                         entries, visits);
                         } else if (((fj >> lane) & 1ull) && acc != 0.0) {
-                            unsafeAtomicAdd(&hacc[(size_t)hr * 64 + lane], acc);
+                            if ((uint32_t)hr < HL)
+                                unsafeAtomicAdd(&L.hl[hr][lane], acc);
+                            else
+                                unsafeAtomicAdd(&hacc[(size_t)(hr - HL) * 64 + lane], acc);
                         }
                     }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -621,8 +634,9 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                         const uint32_t vj = L.ev[j];
                         const uint64_t fj = L.em[j];
                         const uint32_t cnt_v = ((fj >> lane) & 1ull) ? sig[(size_t)vj * 64 + lane] : 0u;
-                        finish_entry(a, psi, vj, fj, hacc[(size_t)h * 64 + lane], cnt_v, my_src, L.ed[j], reached,
-                                     examined, entries, visits);
+                        const double acc = h < HL ? L.hl[h][lane] : hacc[(size_t)(h - HL) * 64 + lane];
+                        finish_entry(psi, bcp, c0 + j, vj, fj, acc, cnt_v, my_src, L.ed[j], reached, examined,
+                                     entries, visits);
                     }
                     __syncthreads();
                     if (tid == 0) L.nhub = 0;
@@ -643,11 +657,21 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
         }
         // ---------------- reset the touched state ----------------
         if (!team_sync(L, ctl, W, a.stats)) break;
+        // entries, thread per entry: mask records, and the BC contributions of finished entries
+        for (uint32_t i = gtid; i < n_entries; i += gthreads) {
+            const uint32_t v = lv[i];
+            const uint64_t m = lm[i];
+            mk.clear(v);
+            if (!stopped && (m & ~ovf)) {
+                const double c = bcp[i];
+                if (c != 0.0) unsafeAtomicAdd(&a.bc[a.iperm ? a.iperm[v] : v], c);
+            }
+        }
+        // counts, lane per source (psi is written before it is read)
         for (uint32_t i = gwave; i < n_entries; i += gwaves) {
             const uint32_t v = lv[i];
             const uint64_t m = lm[i];
-            if ((m >> lane) & 1ull) sig[(size_t)v * 64 + lane] = 0u;   // psi is written before it is read
-            if (lane == 0) mk.clear(v);
+            if ((m >> lane) & 1ull) sig[(size_t)v * 64 + lane] = 0u;
         }
         // sources this kernel did not finish go to the per-source kernel
         if (leader && tid == 0) {
@@ -816,7 +840,7 @@ struct MsbPool {
     TeamCtl* ctl = nullptr;
     uint64_t *masks = nullptr, *lst_m = nullptr;
     uint32_t* sig = nullptr;
-    double* psi = nullptr;
+    double *psi = nullptr, *bcp = nullptr;
     double* hacc = nullptr;
     uint32_t *lst_v = nullptr, *lvl = nullptr;
     uint32_t* plan = nullptr;       // [plan_cap]
@@ -827,12 +851,12 @@ struct MsbPool {
 };
 
 size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels) {
-    return sizeof(TeamCtl) + (size_t)n * (16 + 256 + 512) + 4 * kStaggerWords * 8 + (size_t)cap * 12 +
+    return sizeof(TeamCtl) + (size_t)n * (16 + 256 + 512) + 4 * kStaggerWords * 8 + (size_t)cap * 20 +
            4 * ((size_t)max_levels + 2);
 }
 
 void msb_pool_free(MsbPool& p) {
-    for (void* q : {(void*)p.ctl, (void*)p.masks, (void*)p.sig, (void*)p.psi, (void*)p.lst_m, (void*)p.hacc,
+    for (void* q : {(void*)p.ctl, (void*)p.masks, (void*)p.sig, (void*)p.psi, (void*)p.bcp, (void*)p.lst_m, (void*)p.hacc,
                     (void*)p.lst_v, (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small, (void*)p.bhist})
         if (q) (void)hipFree(q);
     p = MsbPool{};
@@ -873,6 +897,7 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     BC_HIP_TRY(hipMalloc((void**)&p.psi, (size_t)teams * p.psi_stride * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.hacc, (size_t)wgs * hub_rows * 512));
     BC_HIP_TRY(hipMalloc((void**)&p.lst_v, (size_t)teams * cap * 4));
+    BC_HIP_TRY(hipMalloc((void**)&p.bcp, (size_t)teams * cap * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.lst_m, (size_t)teams * cap * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.lvl, (size_t)teams * (max_levels + 2) * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.plan, (size_t)p.plan_cap * 4));
@@ -966,6 +991,7 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.masks = p.masks;
     a.sig = p.sig;
     a.psi = p.psi;
+    a.bcp = p.bcp;
     a.hacc = p.hacc;
     a.lst_v = p.lst_v;
     a.lst_m = p.lst_m;
