@@ -181,11 +181,13 @@ struct GState {
         r.val = 0;
         rec[v] = r;
     }
-    // level boundary: make this workgroup's global writes visible and drop stale L1 lines
+    // level boundary: make this workgroup's global writes visible to its other waves.  A slot
+    // belongs to one workgroup, so workgroup scope is enough; agent scope would write back and
+    // invalidate the whole L2 of the XCD at every level.
     __device__ __forceinline__ void barrier() const {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
 };
 
