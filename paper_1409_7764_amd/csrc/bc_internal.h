@@ -160,6 +160,7 @@ struct WorkDesc {
     const uint32_t* iperm;     // nullable: kernel id -> caller id, applied to every output index
     uint32_t* counters;        // nullable: per-descriptor {done, overflowed, levels_max, bad}
     int32_t n;
+    uint32_t max_in;           // largest in-degree (bounds the counts; 0 = unknown)
     uint32_t item_begin;       // first work item of this descriptor in the launch
     uint32_t num_items;
     uint32_t src_base;

@@ -37,6 +37,8 @@ namespace bcmi {
 namespace {
 
 constexpr uint32_t kPiece = 256;     // hub edges per wavefront work piece
+constexpr int kTpv = 4;              // thread-per-vertex mode: chunks whose largest degree is at most this
+constexpr double kSafeCount = 1.8e19;   // below 2^64 = 1.8447e19
 constexpr uint16_t kUnseen16 = 0xffff;
 
 __device__ __forceinline__ unsigned lane_id() {
@@ -83,6 +85,7 @@ struct Scratch {
     double acc[WG];
     uint32_t tail;             // next free queue position
     uint32_t ovf;              // a 64-bit count carried
+    unsigned long long msig;   // largest count of the level being expanded
     uint32_t item, desc;
 };
 
@@ -158,7 +161,17 @@ struct GState {
         const unsigned long long old = atomicAdd((unsigned long long*)&rec[w].val, (unsigned long long)s);
         return old + s < old;
     }
+    __device__ __forceinline__ void add_u64_nr(uint32_t w, uint64_t s) {
+        __hip_atomic_fetch_add((unsigned long long*)&rec[w].val, (unsigned long long)s, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
     __device__ __forceinline__ void add_f64(uint32_t w, uint64_t s) { unsafeAtomicAdd((double*)&rec[w].val, u2d(s)); }
+    // claim of a vertex whose distance read -1: the CAS decides the first discoverer
+    __device__ __forceinline__ int claim_unseen(uint32_t w, int d1, bool& fresh) {
+        const int old = atomicCAS(&rec[w].dist, -1, d1);
+        fresh = old < 0;
+        return fresh ? d1 : old;
+    }
     __device__ __forceinline__ double psi_if_level(uint32_t w, int d1) const {
         const VRec r = rec[w];
         return r.dist == d1 ? u2d(r.val) : 0.0;
@@ -225,7 +238,12 @@ struct LState {
         const unsigned long long old = atomicAdd((unsigned long long*)&vals[w], (unsigned long long)s);
         return old + s < old;
     }
+    __device__ __forceinline__ void add_u64_nr(uint32_t w, uint64_t s) {
+        __hip_atomic_fetch_add((unsigned long long*)&vals[w], (unsigned long long)s, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
     __device__ __forceinline__ void add_f64(uint32_t w, uint64_t s) { atomicAdd((double*)&vals[w], u2d(s)); }
+    __device__ __forceinline__ int claim_unseen(uint32_t w, int d1, bool& fresh) { return claim(w, d1, fresh); }
     __device__ __forceinline__ double psi_if_level(uint32_t w, int d1) const {
         return dist16[w] == (uint16_t)d1 ? u2d(vals[w]) : 0.0;
     }
@@ -255,7 +273,30 @@ struct LState {
 };
 
 // ---- forward sweep ----------------------------------------------------------------------------
-template <bool F64, int WG, class S>
+// count update of one DAG edge: double precision after a carry; 64-bit without waiting for
+// the old value when the level's bound rules out a carry (SAFE); else with the carry check
+template <bool F64, bool SAFE, int WG, class S>
+__device__ __forceinline__ void add_count(S& st, Scratch<WG>& L, uint32_t w, uint64_t s) {
+    if (F64) st.add_f64(w, s);
+    else if (SAFE) st.add_u64_nr(w, s);
+    else if (st.add_u64(w, s)) L.ovf = 1u;
+}
+
+// wavefront-aggregated append of newly discovered vertices to the queue
+template <int WG, class S>
+__device__ __forceinline__ void append_fresh(S& st, Scratch<WG>& L, bool fresh, uint32_t w) {
+    const uint64_t mask = __ballot(fresh);
+    if (mask) {
+        const unsigned lane = lane_id();
+        const unsigned leader = __builtin_ctzll(mask);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&L.tail, (uint32_t)__builtin_popcountll(mask));
+        base = __shfl(base, leader, 64);
+        if (fresh) st.q_set(base + (uint32_t)__builtin_popcountll(mask & lanemask_lt()), w);
+    }
+}
+
+template <bool F64, bool SAFE, int WG, class S>
 __device__ __forceinline__ void forward_edge(S& st, Scratch<WG>& L, bool ok, uint32_t w, uint64_t s, int d1,
                                              uint32_t& dag) {
     bool fresh = false;
@@ -263,8 +304,7 @@ __device__ __forceinline__ void forward_edge(S& st, Scratch<WG>& L, bool ok, uin
         const int dw = st.claim(w, d1, fresh);
         if (dw == d1) {
             ++dag;
-            if (F64) st.add_f64(w, s);
-            else if (st.add_u64(w, s)) L.ovf = 1u;
+            add_count<F64, SAFE>(st, L, w, s);
         }
     }
     const uint64_t mask = __ballot(fresh);
@@ -278,7 +318,7 @@ __device__ __forceinline__ void forward_edge(S& st, Scratch<WG>& L, bool ok, uin
     }
 }
 
-template <bool F64, int WG, class S>
+template <bool F64, bool SAFE, int WG, class S>
 __device__ void expand_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__ row_ptr,
                              const uint32_t* __restrict__ col, uint32_t lo, uint32_t hi, int d, uint32_t hub,
                              uint32_t tpv_max, uint32_t& exam, uint32_t& dag) {
@@ -300,15 +340,34 @@ __device__ void expand_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__
         const bool is_hub = valid && deg >= hub;
         uint32_t so, stot, po, ptot, mx;
         classify_chunk<WG>(L, deg, is_hub, so, stot, po, ptot, mx);
+        if (!F64) {   // the level's largest count bounds the next levels' sums
+            const uint64_t ms = wave_max<uint64_t>(valid ? sv : 0ull);
+            if (lane == 0 && ms) atomicMax(&L.msig, (unsigned long long)ms);
+        }
         if (ptot == 0 && mx <= tpv_max) {
-            // thread per vertex: every lane walks its own short list
+            // thread per vertex, at most kTpv successors each: every successor's distance is
+            // read, then every claim issued, before the first count update
             const uint32_t my = is_hub ? 0u : deg;
-            const uint32_t wm = wave_max(my);
-            for (uint32_t t = 0; t < wm; ++t) {
-                const bool ok = t < my;
-                const uint32_t w = ok ? col[beg + t] : 0u;
-                forward_edge<F64>(st, L, ok, w, sv, d1, dag);
+            uint32_t w[kTpv];
+            int dw[kTpv];
+            bool fresh[kTpv];
+#pragma unroll
+            for (int t = 0; t < kTpv; ++t) w[t] = (uint32_t)t < my ? col[beg + t] : 0u;
+#pragma unroll
+            for (int t = 0; t < kTpv; ++t) dw[t] = (uint32_t)t < my ? st.dist(w[t]) : 0;
+#pragma unroll
+            for (int t = 0; t < kTpv; ++t) {
+                fresh[t] = false;
+                if ((uint32_t)t < my && dw[t] < 0) dw[t] = st.claim_unseen(w[t], d1, fresh[t]);
             }
+#pragma unroll
+            for (int t = 0; t < kTpv; ++t)
+                if ((uint32_t)t < my && dw[t] == d1) {
+                    ++dag;
+                    add_count<F64, SAFE>(st, L, w[t], sv);
+                }
+#pragma unroll
+            for (int t = 0; t < kTpv; ++t) append_fresh(st, L, fresh[t], w[t]);
             __syncthreads();
             continue;
         }
@@ -329,7 +388,7 @@ __device__ void expand_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__
                 w = col[L.beg[j] + (p - L.scan[j])];
                 s = L.sig[j];
             }
-            forward_edge<F64>(st, L, ok, w, s, d1, dag);
+            forward_edge<F64, SAFE>(st, L, ok, w, s, d1, dag);
         }
         // wavefront per hub piece: lanes read 64 consecutive successors per step
         for (uint32_t pc = wave; pc < ptot; pc += NW) {
@@ -341,7 +400,7 @@ __device__ void expand_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__
             for (uint32_t e = e0; e < e1; e += 64) {
                 const bool ok = e + lane < e1;
                 const uint32_t w = ok ? col[b + e + lane] : 0u;
-                forward_edge<F64>(st, L, ok, w, s, d1, dag);
+                forward_edge<F64, SAFE>(st, L, ok, w, s, d1, dag);
             }
         }
         __syncthreads();
@@ -430,18 +489,29 @@ __device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s,
             st.seed(s, f64 ? d2u(1.0) : 1ull);
             L.tail = 1;
             L.ovf = 0;
+            L.msig = 0;
         }
+        uint64_t msig_prev = 1;   // level 0 holds the source, count 1
+        const double maxin2 = (double)D.max_in * (double)D.max_in;
         st.barrier();
         uint32_t lo = 0, hi = 1;
         int d = 0;
         bool overflowed = false;
         for (;;) {
-            if (f64) expand_level<true, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
-            else expand_level<false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+            // no carry can occur this level if (largest count on level d-1) * maxin^2 < 2^64
+            const bool safe = d == 0 || (D.max_in && (double)msig_prev * maxin2 < kSafeCount);
+            if (f64)
+                expand_level<true, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+            else if (safe)
+                expand_level<false, true, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+            else
+                expand_level<false, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
             st.barrier();
             const uint32_t tail = L.tail;
             const bool ov = L.ovf != 0u;
+            msig_prev = L.msig;
             __syncthreads();
+            if (tid == 0) L.msig = 0;   // ordered before the next level's updates by its first barrier
             if (!f64 && ov) {
                 overflowed = true;
                 count = tail;
@@ -775,7 +845,7 @@ LaunchPlan make_plan(const Knobs& k, uint32_t max_n, uint32_t items, int device)
     grid = std::min<long>(grid, std::max<uint32_t>(items, 1));
     p.grid = (unsigned)std::max<long>(grid, 1);
     p.args.hub = k.hub < 0 ? 0xffffffffu : (uint32_t)std::max(k.hub, 1);
-    p.args.tpv_max = 4;
+    p.args.tpv_max = kTpv;
     p.args.lds_n = p.lds_path ? max_n : 0;
     p.args.zero_outputs = 1;
     return p;
@@ -849,6 +919,7 @@ static void retry_launch(void* ctx, const uint32_t* list, const uint32_t* count,
     d.perm = kernel_ids ? nullptr : g.perm;
     d.iperm = g.iperm;
     d.n = g.n;
+    d.max_in = g.max_in_degree;
     d.num_items = cap;
     BC_HIP_TRY(hipMemcpyAsync(c.gs->rdesc, &d, sizeof(d), hipMemcpyHostToDevice, st));
     p.args.descs = c.gs->rdesc;
@@ -895,6 +966,7 @@ int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     d.iperm = g.iperm;
     d.counters = nullptr;
     d.n = g.n;
+    d.max_in = g.max_in_degree;
     d.item_begin = 0;
     d.num_items = ra.num_items;
     BC_HIP_TRY(hipMemcpyAsync(gs.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
@@ -932,6 +1004,7 @@ int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     d.perm = g.perm;
     d.iperm = g.iperm;
     d.n = g.n;
+    d.max_in = g.max_in_degree;
     d.num_items = ra.num_items;
     BC_HIP_TRY(hipMemcpyAsync(gs.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
     // zero BC and the call counters
@@ -1058,6 +1131,7 @@ static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* b
                 d.sources = nullptr;
                 d.counters = bp->d_counters + 4 * pos;
                 d.n = g->n;
+                d.max_in = g->max_in_degree;
                 d.item_begin = items;
                 d.num_items = (uint32_t)g->n;
                 items += (uint32_t)g->n;

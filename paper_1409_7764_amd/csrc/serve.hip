@@ -175,6 +175,7 @@ struct Server {
                 d.src_base = r.exact ? r.next : 0u;
                 d.counters = r.d_counters;
                 d.n = r.g->n;
+                d.max_in = r.g->max_in_degree;
                 d.item_begin = items[c];
                 d.num_items = take;
                 cls[c].push_back(d);
