@@ -214,6 +214,18 @@ void pool_free(SlotPool& p);
 size_t pool_bytes(uint32_t slot_n, int slots);
 bool lds_fits(const Knobs& k, uint32_t n, int device);
 
+// ---- 64 sources per batch (msb.hip) ---------------------------------------------------------
+struct MsbPool;
+MsbPool* msb_pool_new();
+void msb_pool_delete(MsbPool* p);
+void msb_pool_discard(MsbPool* p);
+size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels);
+// enqueues the per-source launch over the sources a batched launch hands back: (ctx, list,
+// device count, capacity, list holds kernel ids, stream)
+using RetryLaunch = void (*)(void*, const uint32_t*, const uint32_t*, uint32_t, bool, hipStream_t);
+void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
+                     int wg, int team_knob, int slots_cap, hipStream_t st, RetryLaunch retry_launch, void* retry_ctx);
+
 // ---- tuning (tune.hip) -------------------------------------------------------------------
 Knobs resolve_knobs(Graph& g, const bc_tuning* t);
 Knobs default_knobs(const Graph& g);

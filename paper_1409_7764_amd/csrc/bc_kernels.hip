@@ -854,8 +854,6 @@ LaunchPlan make_plan(const Knobs& k, uint32_t max_n, uint32_t items, int device)
 // ---------------------------------------------------------------------------------------
 // single-graph entry (exact / sampled / inspection)
 // ---------------------------------------------------------------------------------------
-struct MsbPool;
-void msb_pool_delete(MsbPool* p);
 
 struct GraphScratch {
     SlotPool pool;
@@ -880,13 +878,7 @@ void graph_scratch_free(Graph& g) {
     g.slots = nullptr;
 }
 
-struct MsbPool;
-MsbPool* msb_pool_new();
-void msb_pool_delete(MsbPool* p);
-void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
-                     int wg, int team_knob, int slots_cap, hipStream_t st,
-                     void (*retry_launch)(void*, const uint32_t*, const uint32_t*, uint32_t, bool, hipStream_t),
-                     void* retry_ctx);
+
 
 // Per-source launch over a device-resident list whose length is known only on the device
 // (sources the batched kernel handed back).
@@ -1022,7 +1014,6 @@ int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     return 2;
 }
 
-void msb_pool_discard(MsbPool* p);
 
 // Drops the batched path's state after a team gave up on a barrier (the state is dirty).
 void graph_discard_batched_state(Graph& g) {

@@ -876,7 +876,9 @@ void msb_pool_discard(MsbPool* p) {
 
 static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t cap, uint32_t max_levels,
                             uint32_t hub_rows, uint32_t plan_cap, hipStream_t st) {
-    if (p.masks && p.n == n && p.teams >= teams && p.wgs >= wgs && p.cap >= cap && p.max_levels >= max_levels &&
+    // a pool built for a larger graph serves a smaller one: its arrays are all zero between
+    // batches, and the kernel takes its strides from the pool
+    if (p.masks && p.n >= n && p.teams >= teams && p.wgs >= wgs && p.cap >= cap && p.max_levels >= max_levels &&
         p.hub_rows >= hub_rows && p.plan_cap >= plan_cap)
         return;
     BC_HIP_TRY(hipStreamSynchronize(st));
@@ -919,9 +921,7 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
 // Enqueues the batched path: source plan, batched sweeps, then the per-source kernel on the
 // sources handed back.  `retry_launch` enqueues that per-source launch over (list, count).
 void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
-                     int wg, int team_knob, int slots_cap, hipStream_t st,
-                     void (*retry_launch)(void*, const uint32_t*, const uint32_t*, uint32_t, bool, hipStream_t),
-                     void* retry_ctx) {
+                     int wg, int team_knob, int slots_cap, hipStream_t st, RetryLaunch retry_launch, void* retry_ctx) {
     const DevInfo& di = dev_info(g.device);
     wg = msb_norm_wg(wg);
     const uint32_t n = (uint32_t)g.n;
@@ -943,7 +943,7 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     size_t free_b = 0, total_b = 0;
     BC_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     const size_t per_team = msb_team_bytes(n, cap, max_levels);
-    const size_t have = p.n == n ? (size_t)p.teams * msb_team_bytes(n, p.cap, p.max_levels) : 0;
+    const size_t have = p.n >= n ? (size_t)p.teams * msb_team_bytes(p.n, p.cap, p.max_levels) : 0;
     const size_t budget = (free_b + have) / 2 - std::min<size_t>((free_b + have) / 2, (size_t)max_wgs * wg * 512);
     teams = (long)std::max<size_t>(1, std::min<size_t>(teams, budget / std::max<size_t>(per_team, 1)));
     const int grid = (int)max_wgs;

@@ -10,8 +10,9 @@
 //      small requests are not queued behind large ones;
 //   3. launches the tick as one persistent launch per state home (LDS-resident for small
 //      graphs, global-memory slots for the rest) over a work list that mixes requests and
-//      graphs; up to two ticks are queued on the stream so the device never waits for the
-//      host;
+//      graphs, plus one batched launch (64 sources per wavefront) per chunk of a request on
+//      a larger, shallow graph; up to two ticks are queued on the stream so the device never
+//      waits for the host;
 //   4. when a tick's event has fired, requests whose last chunk it held are complete; their
 //      device counters (copied back by the tick itself) fill the poll() record.
 #include "bc_internal.h"
@@ -24,6 +25,7 @@
 #include <unordered_map>
 
 namespace bcmi {
+struct Server;
 namespace {
 
 using Clock = std::chrono::steady_clock;
@@ -38,6 +40,7 @@ struct Request {
     double* d_bc = nullptr;
     size_t footprint = 0;
     bool lds = false;
+    bool batched = false;              // chunks run by the batched kernel
     RState state = RState::Queued;
     uint32_t* d_sources = nullptr;
     uint32_t* d_counters = nullptr;    // {done, overflowed, levels_max, bad}
@@ -53,6 +56,13 @@ struct Chunk {
     bool last;                         // this chunk completes the request
 };
 
+constexpr uint32_t kChunkGlobal = 64;     // sources per chunk on the global-slot path
+constexpr uint32_t kChunkLds = 1024;      // sources per chunk on the LDS-resident path
+constexpr uint32_t kChunkBatched = 1024;  // sources per chunk on the batched path (16 batches)
+constexpr uint32_t kTickDescs = 4096;     // chunks per tick
+constexpr uint32_t kTickBatched = 8;      // batched chunks per tick
+constexpr int kServeTeams = 32;           // state slots of the batched path
+
 struct Tick {
     bool busy = false;
     hipEvent_t done = nullptr;
@@ -61,6 +71,13 @@ struct Tick {
     WorkDesc* d_desc = nullptr;
     CallStats* d_stats = nullptr;      // one per launch class
     uint32_t cap = 0;
+    // batched chunks: two stats blocks each (batched launch, hand-off launch), the hand-off
+    // launch's descriptor, and a flag raised when a batched team gave up at a barrier
+    CallStats* d_bstats = nullptr;     // [2 * kTickBatched]
+    WorkDesc* h_rdesc = nullptr;       // pinned [kTickBatched]
+    WorkDesc* d_rdesc = nullptr;
+    uint32_t* d_flag = nullptr;
+    uint32_t* h_flag = nullptr;        // pinned
 };
 
 __global__ void k_zero_f64(double* p, uint32_t n) {
@@ -74,9 +91,26 @@ __global__ void k_zero_stats(CallStats* s, uint32_t count) {
     for (uint32_t i = threadIdx.x; i < count * (sizeof(CallStats) / 4); i += blockDim.x) w[i] = 0u;
 }
 
-constexpr uint32_t kChunkGlobal = 64;     // sources per chunk on the global-slot path
-constexpr uint32_t kChunkLds = 1024;      // sources per chunk on the LDS-resident path
-constexpr uint32_t kTickDescs = 4096;     // chunks per tick
+// a batched chunk's counters into its request's {done, overflowed, levels_max, bad}
+__global__ void k_fold_counters(const CallStats* b, const CallStats* h, uint32_t* counters, uint32_t* flag) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    counters[0] += b->n_done + h->n_done;
+    counters[1] += b->n_overflow + h->n_overflow;
+    counters[2] = max(counters[2], max(b->levels_max, h->levels_max));
+    counters[3] += b->bad_source + h->bad_source;
+    if (b->pad[0]) *flag = 1u;
+}
+
+// hand-off of a batched chunk's unfinished sources to the per-source kernel
+struct HandOff {
+    Server* s;
+    const Request* r;
+    CallStats* stats;
+    WorkDesc* h_desc;
+    WorkDesc* d_desc;
+};
+void serve_hand_off(void* ctx, const uint32_t* list, const uint32_t* count, uint32_t cap, bool kernel_ids,
+                    hipStream_t st);
 
 }  // namespace
 
@@ -96,15 +130,20 @@ struct Server {
     Clock::time_point t0;
     Knobs knobs;
     SlotPool pool;
+    MsbPool* msb = nullptr;
     Tick ticks[2];
     std::string fatal;
 
     double now_ms() const { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
 
-    size_t footprint(const Graph& g, uint32_t k, bool lds) const {
+    size_t footprint(const Graph& g, uint32_t k, bool lds, bool batched) const {
         const size_t n = (size_t)g.n, m = g.m;
         size_t f = 2 * (4 * (n + 1) + 4 * m) + 8 * n;
-        if (!lds) f += (size_t)std::min<uint32_t>(k, kChunkGlobal) * (24 * n + 4);
+        if (batched)
+            f += (size_t)std::min<uint32_t>((k + 63) / 64, kServeTeams) *
+                 msb_team_bytes((uint32_t)n, (uint32_t)std::min<uint64_t>(8 * n + 64, 0xffffffffull), 1024);
+        else if (!lds)
+            f += (size_t)std::min<uint32_t>(k, kChunkGlobal) * (24 * n + 4);
         return f;
     }
 
@@ -151,17 +190,39 @@ struct Server {
     // Builds and launches one tick from the admitted requests (lock held).
     void launch_tick_locked(Tick& tk) {
         std::vector<WorkDesc> cls[2];     // 0: LDS-resident, 1: global slots
-        std::vector<Chunk> chunks[2];
+        std::vector<Chunk> chunks[3];     // 2: batched
         uint32_t items[2] = {0, 0}, maxn[2] = {0, 0};
         // a tick holds about one round of the persistent grid, so its duration is bounded and a
         // request arriving meanwhile starts within roughly one source's search time
         const uint32_t item_cap[2] = {1u << 16, (uint32_t)std::max(1, max_slots)};
+        struct BRun {
+            uint64_t ticket;
+            const uint32_t* sources;
+            uint32_t take;
+            bool last;
+        };
+        std::vector<BRun> bruns;
         bool progress = true;
         while (progress && cls[0].size() + cls[1].size() < kTickDescs) {
             progress = false;
             for (uint64_t t : active) {
                 Request& r = reqs[t];
                 if (r.next >= r.k) continue;
+                if (r.batched) {   // one batched chunk per request and tick
+                    if (bruns.size() >= kTickBatched) continue;
+                    bool has = false;
+                    for (const BRun& b : bruns) has |= b.ticket == t;
+                    if (has) continue;
+                    const uint32_t take = std::min(r.k - r.next, kChunkBatched);
+                    // exact requests run the vertices in the graph's batching order
+                    const uint32_t* src = r.exact ? r.g->order + r.next : r.d_sources + r.next;
+                    r.next += take;
+                    r.inflight += 1;
+                    if (r.t_start < 0) r.t_start = now_ms();
+                    bruns.push_back(BRun{t, src, take, r.next >= r.k});
+                    progress = true;
+                    continue;
+                }
                 const int c = r.lds ? 0 : 1;
                 if (items[c] >= item_cap[c]) continue;
                 const uint32_t take = std::min(r.k - r.next, r.lds ? kChunkLds : kChunkGlobal);
@@ -190,12 +251,14 @@ struct Server {
             }
         }
         const size_t nd = cls[0].size() + cls[1].size();
-        if (nd == 0) return;
-        for (size_t i = 0; i < cls[0].size(); ++i) tk.h_desc[i] = cls[0][i];
-        for (size_t i = 0; i < cls[1].size(); ++i) tk.h_desc[cls[0].size() + i] = cls[1][i];
-        BC_HIP_TRY(hipMemcpyAsync(tk.d_desc, tk.h_desc, sizeof(WorkDesc) * nd, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, st, tk.d_stats, 2u);
-        BC_HIP_TRY(hipGetLastError());
+        if (nd == 0 && bruns.empty()) return;
+        if (nd) {
+            for (size_t i = 0; i < cls[0].size(); ++i) tk.h_desc[i] = cls[0][i];
+            for (size_t i = 0; i < cls[1].size(); ++i) tk.h_desc[cls[0].size() + i] = cls[1][i];
+            BC_HIP_TRY(hipMemcpyAsync(tk.d_desc, tk.h_desc, sizeof(WorkDesc) * nd, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, st, tk.d_stats, 2u);
+            BC_HIP_TRY(hipGetLastError());
+        }
         for (int c = 0; c < 2; ++c) {
             if (cls[c].empty()) continue;
             Knobs k = knobs;
@@ -220,8 +283,23 @@ struct Server {
             p.args.zero_outputs = 0;   // outputs were zeroed at admission; requests span ticks
             enqueue_plan(p, st, 0);
         }
+        // batched chunks after the per-source work of the tick, so small requests go first
+        hipLaunchKernelGGL(k_zero_small, dim3(1), dim3(64), 0, st, tk.d_flag, 1u);
+        for (size_t i = 0; i < bruns.size(); ++i) {
+            const BRun& b = bruns[i];
+            Request& r = reqs[b.ticket];
+            CallStats* bs = tk.d_bstats + 2 * i;
+            hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, st, bs, 2u);
+            BC_HIP_TRY(hipGetLastError());
+            HandOff h{this, &r, bs + 1, tk.h_rdesc + i, tk.d_rdesc + i};
+            run_msb_enqueue(*msb, *r.g, b.sources, b.take, r.d_bc, bs, knobs.batch_wg, 0, kServeTeams, st,
+                            serve_hand_off, &h);
+            hipLaunchKernelGGL(k_fold_counters, dim3(1), dim3(1), 0, st, bs, bs + 1, r.d_counters, tk.d_flag);
+            BC_HIP_TRY(hipGetLastError());
+        }
         tk.chunks.clear();
-        for (int c = 0; c < 2; ++c)
+        for (const BRun& b : bruns) chunks[2].push_back(Chunk{b.ticket, b.last});
+        for (int c = 0; c < 3; ++c)
             for (const Chunk& ch : chunks[c]) {
                 tk.chunks.push_back(ch);
                 if (ch.last) {
@@ -230,12 +308,19 @@ struct Server {
                                               hipMemcpyDeviceToHost, st));
                 }
             }
+        BC_HIP_TRY(hipMemcpyAsync(tk.h_flag, tk.d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         BC_HIP_TRY(hipEventRecord(tk.done, st));
         tk.busy = true;
     }
 
     void reap_locked(Tick& tk) {
         const double t = now_ms();
+        if (*tk.h_flag) {   // a batched team gave up waiting at a barrier: its state is dirty
+            msb_pool_discard(msb);
+            tk.chunks.clear();
+            tk.busy = false;
+            throw Error{BC_E_HIP, "batched launch: a team gave up waiting at a barrier"};
+        }
         for (const Chunk& ch : tk.chunks) {
             auto it = reqs.find(ch.ticket);
             if (it == reqs.end()) continue;
@@ -301,6 +386,44 @@ struct Server {
     }
 };
 
+namespace {
+void serve_hand_off(void* ctx, const uint32_t* list, const uint32_t* count, uint32_t cap, bool kernel_ids,
+                    hipStream_t st) {
+    HandOff& h = *reinterpret_cast<HandOff*>(ctx);
+    Server& s = *h.s;
+    const Graph& g = *h.r->g;
+    Knobs k = s.knobs;
+    k.lds_max_n = -1;
+    k.teams = 64;
+    LaunchPlan p = make_plan(k, (uint32_t)g.n, cap, s.device);
+    if (!s.pool.rec || s.pool.slot_n < (uint32_t)g.n || s.pool.slots < (int)p.grid)
+        pool_ensure(s.pool, std::max((uint32_t)g.n, s.pool.slot_n), std::max<int>(p.grid, s.pool.slots), st);
+    p.args.rec = s.pool.rec;
+    p.args.queue = s.pool.queue;
+    p.args.lvl = s.pool.lvl;
+    p.args.slot_n = s.pool.slot_n;
+    WorkDesc d{};
+    d.row_ptr = g.krow();
+    d.col = g.kcol();
+    d.bc = h.r->d_bc;
+    d.sources = list;
+    d.perm = kernel_ids ? nullptr : g.perm;
+    d.iperm = g.iperm;
+    d.n = g.n;
+    d.max_in = g.max_in_degree;
+    d.num_items = cap;
+    *h.h_desc = d;   // pinned: stays valid until the tick completes
+    BC_HIP_TRY(hipMemcpyAsync(h.d_desc, h.h_desc, sizeof(WorkDesc), hipMemcpyHostToDevice, st));
+    p.args.descs = h.d_desc;
+    p.args.ndesc = 1;
+    p.args.total_items = 0;
+    p.args.items_dev = count;   // the batched launch wrote how many sources it handed back
+    p.args.stats = h.stats;
+    p.args.zero_outputs = 0;
+    enqueue_plan(p, st, 0);
+}
+}  // namespace
+
 }  // namespace bcmi
 
 using namespace bcmi;
@@ -345,8 +468,15 @@ bc_status bc_serve_create(size_t hbm_budget_bytes, int32_t max_slots, bc_server*
                 BC_HIP_TRY(hipHostMalloc((void**)&tk.h_desc, sizeof(WorkDesc) * kTickDescs, hipHostMallocDefault));
                 BC_HIP_TRY(hipMalloc((void**)&tk.d_desc, sizeof(WorkDesc) * kTickDescs));
                 BC_HIP_TRY(hipMalloc((void**)&tk.d_stats, sizeof(CallStats) * 2));
+                BC_HIP_TRY(hipMalloc((void**)&tk.d_bstats, sizeof(CallStats) * 2 * kTickBatched));
+                BC_HIP_TRY(hipHostMalloc((void**)&tk.h_rdesc, sizeof(WorkDesc) * kTickBatched, hipHostMallocDefault));
+                BC_HIP_TRY(hipMalloc((void**)&tk.d_rdesc, sizeof(WorkDesc) * kTickBatched));
+                BC_HIP_TRY(hipMalloc((void**)&tk.d_flag, sizeof(uint32_t)));
+                BC_HIP_TRY(hipHostMalloc((void**)&tk.h_flag, sizeof(uint32_t), hipHostMallocDefault));
+                *tk.h_flag = 0;
                 tk.cap = kTickDescs;
             }
+            s->msb = msb_pool_new();
             s->t0 = Clock::now();
             s->th = std::thread([s] { s->loop(); });
         } catch (...) {
@@ -376,7 +506,9 @@ bc_status bc_serve_submit(bc_server sh, bc_graph gh, const uint32_t* h_sources, 
         }
         r.d_bc = d_bc;
         r.lds = lds_fits(s->knobs, (uint32_t)g->n, s->device);
-        r.footprint = s->footprint(*g, r.k, r.lds);
+        // larger shallow graphs with at least one full batch of sources: 64 per wavefront
+        r.batched = !r.lds && g->order && !g->deep && r.k >= 64 && s->knobs.batched >= 0;
+        r.footprint = s->footprint(*g, r.k, r.lds, r.batched);
         BC_REQUIRE(r.footprint <= s->budget, BC_E_NOMEM, "request footprint exceeds the server budget");
         std::lock_guard<std::mutex> lk(s->mu);
         BC_REQUIRE(!s->stopping, BC_E_STATE, "server is stopping");
@@ -406,7 +538,7 @@ bc_status bc_serve_poll(bc_server sh, uint64_t ticket, bc_info* info) {
             o.n_sources = r.h_counters[0];
             o.n_sigma_fp64_fallback = r.h_counters[1];
             o.levels_max = r.h_counters[2];
-            o.path = r.lds ? 1u : 0u;
+            o.path = r.batched ? 2u : (r.lds ? 1u : 0u);
             o.kernel_ms = r.t_done - r.t_start;
             o.t_submit_ms = r.t_submit;
             o.t_start_ms = r.t_start;
@@ -440,8 +572,14 @@ bc_status bc_serve_destroy(bc_server sh) {
             if (tk.h_desc) (void)hipHostFree(tk.h_desc);
             if (tk.d_desc) (void)hipFree(tk.d_desc);
             if (tk.d_stats) (void)hipFree(tk.d_stats);
+            if (tk.d_bstats) (void)hipFree(tk.d_bstats);
+            if (tk.h_rdesc) (void)hipHostFree(tk.h_rdesc);
+            if (tk.d_rdesc) (void)hipFree(tk.d_rdesc);
+            if (tk.d_flag) (void)hipFree(tk.d_flag);
+            if (tk.h_flag) (void)hipHostFree(tk.h_flag);
         }
         pool_free(s->pool);
+        msb_pool_delete(s->msb);
         (void)hipStreamDestroy(s->st);
         delete s;
         return BC_OK;

@@ -33,10 +33,20 @@ def wait(bc, srv, ticket, timeout=120.0):
         time.sleep(0.0005)
 
 
-def footprint(n, m, k, lds):
+def msb_team_bytes(n):
+    """Device state of one batched team: control block, masks 16n + counts 256n + psi 512n,
+    staggers, level lists (8n + 64 entries of 20 B) and 1026 level offsets."""
+    cap = 8 * n + 64
+    return 128 + n * (16 + 256 + 512) + 4 * 37 * 512 * 8 + cap * 20 + 4 * (1024 + 2)
+
+
+def footprint(n, m, k, path):
+    """Admission footprint: CSR + CSC + output, plus the state of the request's path."""
     f = 2 * (4 * (n + 1) + 4 * m) + 8 * n
-    if not lds:
+    if path == "global":
         f += min(k, 64) * (24 * n + 4)
+    elif path == "batched":
+        f += min((k + 63) // 64, 32) * msb_team_bytes(n)
     return f
 
 
@@ -57,6 +67,8 @@ def test_serve_alone_equals_mix(bc):
             reqs.append((gi, None))
         else:
             reqs.append((gi, gg.uniform_sources(n, int(rng.integers(1, 300)), 100 + i)))
+    # fewer than 64 sources on the larger graphs: one source per workgroup in global slots
+    reqs += [(3, gg.uniform_sources(graphs[3].n, 10, 500)), (4, gg.uniform_sources(graphs[4].n, 37, 501))]
     alone = []
     for gi, S in reqs:
         g = graphs[gi]
@@ -66,6 +78,7 @@ def test_serve_alone_equals_mix(bc):
     outs = [torch.full((graphs[gi].n,), -1.0, dtype=torch.float64, device="cuda") for gi, _ in reqs]
     tickets = [bc.bc_serve_submit(srv, graphs[gi], S, out) for (gi, S), out in zip(reqs, outs)]
     infos = [wait(bc, srv, t) for t in tickets]
+    assert {inf["path"] for inf in infos} == {0, 1, 2}   # LDS, global slots and batched in one mix
     for i, ((gi, S), out, inf) in enumerate(zip(reqs, outs, infos)):
         got = out.cpu().numpy()
         rel_close(got, alone[i], what=f"request {i} alone vs mix")
@@ -114,12 +127,13 @@ def test_serve_admission_budget(bc):
     import torch
     n, u, v = gg.rmat(13, 8, 9)
     g = bc.bc_build_csr(n, u, v)
-    f = footprint(g.n, g.m, 512, lds=False)
+    f = footprint(g.n, g.m, 512, path="batched")   # 512 sources on an 8192-vertex R-MAT: batched
     srv = bc.bc_serve_create(int(1.5 * f))       # room for one request at a time
     outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for _ in range(3)]
     S = [gg.uniform_sources(g.n, 512, 20 + i) for i in range(3)]
     ts = [bc.bc_serve_submit(srv, g, S[i], outs[i]) for i in range(3)]
     infos = [wait(bc, srv, t) for t in ts]
+    assert all(i["path"] == 2 for i in infos)
     for a, b in zip(infos, infos[1:]):
         assert b["t_start_ms"] >= a["t_done_ms"]       # admitted only after the previous one left
     for i in range(3):
