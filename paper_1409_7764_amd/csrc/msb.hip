@@ -154,6 +154,7 @@ struct MsbLds {
     int32_t eh[WG];         // accumulator row of a split entry, -1 otherwise
     uint32_t hub_ent[WG];   // accumulator row -> chunk entry
     double hl[WG / 8][64];  // the first accumulator rows (LDS atomics: no wait on memory)
+    unsigned long long ws[WG / 64][4];   // per wavefront: reached pairs, examined, entries, visits
     uint32_t nhub;
     uint32_t chunk;
     uint32_t ok;            // 0 once the team gave up on a barrier
@@ -311,9 +312,10 @@ __device__ __forceinline__ void fwd_units(const MsbArgs& a, MsbLds<WG>& L, const
     const uint32_t lB = actB ? lane : (uint32_t)__builtin_ctzll(fB | (1ull << 63));
     const uint32_t sA = sig[(size_t)vA * 64 + lA];
     const uint32_t sB = sig[(size_t)vB * 64 + lB];
-    const uint32_t wA = a.col[okA ? eA : e1A - 1];
-    const uint32_t wB = a.col[okB ? eB : (e1B > e0B ? e1B - 1 : 0u)];
+    const uint32_t wA0 = a.col[okA ? eA : e1A - 1];
+    const uint32_t wB0 = a.col[okB ? eB : (e1B > e0B ? e1B - 1 : 0u)];
     __builtin_amdgcn_sched_barrier(0);   // the four independent loads above go out first
+    const uint32_t wA = okA ? wA0 : vA, wB = okB ? wB0 : vB;   // valid vertex ids only
     const ulonglong2 qA = mk.both(wA);
     const ulonglong2 qB = mk.both(wB);
     const uint32_t svA = actA ? sA : 0u, svB = actB ? sB : 0u;
@@ -335,26 +337,26 @@ __device__ __forceinline__ void fwd_units(const MsbArgs& a, MsbLds<WG>& L, const
 
 // finishes list entry idx = (v, f) of level d with the summed successor psi in `acc`;
 // `count` is this lane's sigma_s(v), read by the caller
-__device__ __forceinline__ void finish_entry(double* psi, double* bcp, uint32_t idx, uint32_t v, uint64_t f,
-                                             double acc, uint32_t count, uint32_t my_src, uint32_t deg,
-                                             uint32_t& reached, uint64_t& examined, uint32_t& entries,
-                                             uint64_t& visits) {
+__device__ __forceinline__ void finish_entry(uint32_t* sig, double* psi, double* bcp, uint32_t idx, uint32_t v,
+                                             uint64_t f, double acc, uint32_t count, uint32_t my_src,
+                                             uint32_t deg, unsigned long long* ws) {
     const unsigned lane = lane_id();
     double c = 0.0;
     if ((f >> lane) & 1ull) {
         const double sigma = (double)count;
         const double delta = sigma * acc;
         psi[(size_t)v * 64 + lane] = (1.0 + delta) / sigma;
+        sig[(size_t)v * 64 + lane] = 0u;   // the count's last use: cleared for the next batch
         if (my_src != v) c = delta;
     }
     c = wave_sum(c);
     if (lane == 0) {
         bcp[idx] = c;   // added to BC[v] when the batch is reset: no atomic in the sweep
         const uint32_t pc = (uint32_t)__builtin_popcountll(f);
-        reached += pc;
-        examined += (uint64_t)pc * deg;
-        entries += 1;
-        visits += deg;
+        atomicAdd(&ws[0], (unsigned long long)pc);   // this wavefront's counters, in LDS
+        atomicAdd(&ws[1], (unsigned long long)pc * deg);
+        atomicAdd(&ws[2], 1ull);
+        atomicAdd(&ws[3], (unsigned long long)deg);
     }
 }
 
@@ -408,11 +410,12 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     uint32_t* lvl = a.lvl + (size_t)team * (a.max_levels + 2);
     const uint32_t gtid = member * WG + tid, gthreads = W * WG;
     const uint32_t gwave = member * NW + wave, gwaves = W * NW;
-    uint32_t reached = 0, dagc = 0, entries = 0;
-    uint64_t examined = 0, visits = 0;
+    uint32_t dagc = 0;
     uint32_t n_done = 0, levels_max = 0, scans = 0;
     uint64_t cyc[3] = {0, 0, 0};   // thread 0: clock cycles in forward, backward, reset
 
+    if (lane == 0)
+        for (int q = 0; q < 4; ++q) L.ws[wave][q] = 0ull;
     if (tid == 0) {
         L.nhub = 0;
         L.ovf = 0;
@@ -616,8 +619,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                             for (int t = 0; t < kPsiLoads; ++t) acc += x[t];
                         }
                         if (hr < 0) {
-                            finish_entry(psi, bcp, c0 + j, vj, fj, acc, cnt_v, my_src, dj, reached, examined,
-                                         entries, visits);
+                            finish_entry(sig, psi, bcp, c0 + j, vj, fj, acc, cnt_v, my_src, dj, L.ws[wave]);
                         } else if (((fj >> lane) & 1ull) && acc != 0.0) {
                             if ((uint32_t)hr < HL)
                                 unsafeAtomicAdd(&L.hl[hr][lane], acc);
@@ -635,8 +637,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                         const uint64_t fj = L.em[j];
                         const uint32_t cnt_v = ((fj >> lane) & 1ull) ? sig[(size_t)vj * 64 + lane] : 0u;
                         const double acc = h < HL ? L.hl[h][lane] : hacc[(size_t)(h - HL) * 64 + lane];
-                        finish_entry(psi, bcp, c0 + j, vj, fj, acc, cnt_v, my_src, L.ed[j], reached, examined,
-                                     entries, visits);
+                        finish_entry(sig, psi, bcp, c0 + j, vj, fj, acc, cnt_v, my_src, L.ed[j], L.ws[wave]);
                     }
                     __syncthreads();
                     if (tid == 0) L.nhub = 0;
@@ -667,12 +668,15 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 if (c != 0.0) unsafeAtomicAdd(&a.bc[a.iperm ? a.iperm[v] : v], c);
             }
         }
-        // counts, lane per source (psi is written before it is read)
-        for (uint32_t i = gwave; i < n_entries; i += gwaves) {
-            const uint32_t v = lv[i];
-            const uint64_t m = lm[i];
-            if ((m >> lane) & 1ull) sig[(size_t)v * 64 + lane] = 0u;
-        }
+        // counts, lane per source: the backward sweep cleared those of finished entries; what
+        // remains are the flagged sources' (psi is written before it is read)
+        const uint64_t left = stopped ? ~0ull : ovf;
+        if (left)
+            for (uint32_t i = gwave; i < n_entries; i += gwaves) {
+                const uint32_t v = lv[i];
+                const uint64_t m = lm[i] & left;
+                if ((m >> lane) & 1ull) sig[(size_t)v * 64 + lane] = 0u;
+            }
         // sources this kernel did not finish go to the per-source kernel
         if (leader && tid == 0) {
             if (ovf) {
@@ -693,19 +697,14 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
         cyc[2] += clock64() - t_phase;
     }
     // counters of everything this workgroup finished
-    const uint32_t r_w = wave_sum_u32(reached), g_w = wave_sum_u32(dagc), n_w = wave_sum_u32(entries);
-    uint64_t e_w = examined, v_w = visits;
-#pragma unroll
-    for (int dsh = 32; dsh > 0; dsh >>= 1) {
-        e_w += (uint64_t)__shfl_xor((long long)e_w, dsh, 64);
-        v_w += (uint64_t)__shfl_xor((long long)v_w, dsh, 64);
-    }
+    const uint32_t g_w = wave_sum_u32(dagc);
     if (lane == 0) {
-        if (r_w) atomicAdd((unsigned long long*)&a.stats->reached, (unsigned long long)r_w);
-        if (e_w) atomicAdd((unsigned long long*)&a.stats->examined, (unsigned long long)e_w);
+        const unsigned long long r_w = L.ws[wave][0], e_w = L.ws[wave][1], n_w = L.ws[wave][2], v_w = L.ws[wave][3];
+        if (r_w) atomicAdd((unsigned long long*)&a.stats->reached, r_w);
+        if (e_w) atomicAdd((unsigned long long*)&a.stats->examined, e_w);
         if (g_w) atomicAdd((unsigned long long*)&a.stats->dag_edges, (unsigned long long)g_w);
-        if (n_w) atomicAdd((unsigned long long*)&a.stats->entries, (unsigned long long)n_w);
-        if (v_w) atomicAdd((unsigned long long*)&a.stats->edge_visits, (unsigned long long)v_w);
+        if (n_w) atomicAdd((unsigned long long*)&a.stats->entries, n_w);
+        if (v_w) atomicAdd((unsigned long long*)&a.stats->edge_visits, v_w);
     }
     if (tid == 0) {
         if (n_done) atomicAdd(&a.stats->n_done, n_done);
