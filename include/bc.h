@@ -88,6 +88,8 @@ typedef struct {
     uint64_t batch_entries;         /* path 2: (vertex, level) entries of the batches' lists */
     uint64_t batch_edge_visits;     /* path 2: out-edges of those entries */
     uint64_t batch_scans;           /* path 2: level-collect passes (each reads every vertex's masks) */
+    uint64_t batch_handoffs;        /* path 2: sources handed to the one-source-per-workgroup kernel
+                                       (32-bit count cap, list capacity or level cap) */
     uint64_t batch_cycles[3];       /* path 2: workgroup clock cycles summed over workgroups, in the
                                        forward sweep, the backward sweep, and state reset */
 } bc_info;

@@ -41,6 +41,7 @@ class bc_info(ctypes.Structure):
                 ("t_done_ms", ctypes.c_double), ("reached", ctypes.c_uint64), ("examined", ctypes.c_uint64),
                 ("dag_edges", ctypes.c_uint64), ("batch_entries", ctypes.c_uint64),
                 ("batch_edge_visits", ctypes.c_uint64), ("batch_scans", ctypes.c_uint64),
+                ("batch_handoffs", ctypes.c_uint64),
                 ("batch_cycles", ctypes.c_uint64 * 3)]
 
     def as_dict(self):

@@ -113,7 +113,7 @@ void graph_discard_batched_state(Graph& g);
 static void fill_info(Graph& g, hipStream_t st, int path, double ms, uint32_t expected, bc_info* info) {
     CallStats cs;
     read_stats(g, st, &cs);
-    if (cs.pad[0]) {
+    if (cs.aborted) {
         graph_discard_batched_state(g);
         throw Error{BC_E_HIP, "batched kernel: a team of workgroups stopped waiting at a level barrier"};
     }
@@ -131,6 +131,7 @@ static void fill_info(Graph& g, hipStream_t st, int path, double ms, uint32_t ex
     out.batch_entries = cs.entries;
     out.batch_edge_visits = cs.edge_visits;
     out.batch_scans = cs.scans;
+    out.batch_handoffs = cs.handoffs;
     for (int i = 0; i < 3; ++i) out.batch_cycles[i] = cs.cycles[i];
     *info = out;
 }

@@ -60,7 +60,8 @@ struct CallStats {
     uint32_t levels_max;     // deepest search
     uint32_t bad_source;     // sources with id >= n (skipped)
     uint32_t work_head2;     // work counter of a follow-up launch in the same call
-    uint32_t pad[2];         // pad[0]: a batched team gave up waiting at a barrier
+    uint32_t aborted;        // a batched team gave up waiting at a barrier
+    uint32_t handoffs;       // batched path: sources handed to the per-source kernel
     uint64_t reached;        // sum over sources of reached vertices (source included)
     uint64_t examined;       // sum over sources of out-edges of reached vertices
     uint64_t dag_edges;      // sum over sources of shortest-path DAG edges

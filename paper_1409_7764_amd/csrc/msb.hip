@@ -195,7 +195,7 @@ __device__ bool team_sync(MsbLds<WG>& L, TeamCtl* c, uint32_t W, CallStats* stat
             if (ld_team(&c->abort)) ok = 0;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        if (!ok) atomicOr(&stats->pad[0], 1u);
+        if (!ok) atomicOr(&stats->aborted, 1u);
         L.ok = ok;
     }
     __syncthreads();
@@ -682,6 +682,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             if (ovf) {
                 const uint32_t cnt = (uint32_t)__builtin_popcountll(ovf);
                 uint32_t pos = atomicAdd(a.retry_count, cnt);
+                atomicAdd(&a.stats->handoffs, cnt);
                 uint64_t m = ovf;
                 while (m) {
                     const int s = __builtin_ctzll(m);

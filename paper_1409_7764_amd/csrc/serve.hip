@@ -98,7 +98,7 @@ __global__ void k_fold_counters(const CallStats* b, const CallStats* h, uint32_t
     counters[1] += b->n_overflow + h->n_overflow;
     counters[2] = max(counters[2], max(b->levels_max, h->levels_max));
     counters[3] += b->bad_source + h->bad_source;
-    if (b->pad[0]) *flag = 1u;
+    if (b->aborted) *flag = 1u;
 }
 
 // hand-off of a batched chunk's unfinished sources to the per-source kernel

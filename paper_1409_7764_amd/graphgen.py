@@ -162,3 +162,32 @@ def diamond_chain(k: int):
         us += [j, j, a, b]
         vs += [a, b, nxt, nxt]
     return _as_coo(3 * k + 1, us, vs)
+
+
+def wide_diamond_forest(copies: int, width: int, k: int):
+    """`copies` chains of `k` diamonds with `width` middle vertices each; the last joint of
+    every chain feeds one shared sink, which has one out-edge to a tail vertex.  Joint i of a
+    chain has width**i shortest paths from the chain's first joint, while every vertex
+    reaches the sink within 2k + 1 steps (a shallow graph with large path counts; the sink is
+    the vertex of largest in-degree among those with out-edges).
+
+    Chain c starts at b = c * (k * (width + 1) + 1): joint i is b + i * (width + 1), the
+    middles of diamond i are b + i * (width + 1) + 1 .. + width.  The sink is vertex
+    copies * (k * (width + 1) + 1), the tail the next one; n = that + 2.
+    """
+    per = k * (width + 1) + 1
+    sink = copies * per
+    us, vs = [], []
+    for c in range(copies):
+        b = c * per
+        for i in range(k):
+            j = b + i * (width + 1)
+            nxt = j + width + 1
+            for t in range(1, width + 1):
+                us += [j, j + t]
+                vs += [j + t, nxt]
+        us.append(b + k * (width + 1))
+        vs.append(sink)
+    us.append(sink)
+    vs.append(sink + 1)
+    return _as_coo(sink + 2, us, vs)

@@ -201,6 +201,22 @@ def test_batched_state_reuse(bc, team):
     g.free()
 
 
+def test_batched_flagged_counts_shallow_graph(bc):
+    """A shallow graph whose path counts pass 2^32: the automatic path is the batched kernel,
+    which flags those sources (32-bit counts) and hands them to the per-source kernel."""
+    n, u, v = gg.wide_diamond_forest(40, 16, 8)   # counts up to 16^8 = 2^32; 5,482 vertices
+    want, ovf, st = oracle_exact("wide_diamond_40_16_8", n, u, v)
+    say("flagged counts, n", n)
+    g = bc.bc_build_csr(n, u, v)
+    got, info = bc.bc_exact(g, info=True)
+    assert info["path"] == 2 and info["n_sources"] == n
+    assert info["batch_handoffs"] >= 40          # at least every chain's first joint
+    assert info["n_sigma_fp64_fallback"] == int(ovf.sum()) == 0
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    rel_close(np_of(got), want, what="flagged counts")
+    g.free()
+
+
 def test_relabelled_graph_every_path(bc):
     """Graphs from 16,384 vertices run on an internally renumbered copy; every output must
     still come back in the caller's vertex ids."""

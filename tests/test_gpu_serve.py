@@ -123,6 +123,22 @@ def test_serve_overlap_and_continuous_batching(bc):
     small.free()
 
 
+def test_serve_batched_with_hand_off(bc):
+    """An exact request on a shallow 5,482-vertex graph runs as batched chunks; sources whose
+    counts pass 32 bits are handed to the per-source kernel within the same tick."""
+    import torch
+    n, u, v = gg.wide_diamond_forest(40, 16, 8)
+    g = bc.bc_build_csr(n, u, v)
+    srv = bc.bc_serve_create(64 << 30)
+    out = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+    info = wait(bc, srv, bc.bc_serve_submit(srv, g, None, out))
+    assert info["path"] == 2 and info["n_sources"] == n
+    want, _, _ = oracle.bc(oracle.Graph(n, u, v))
+    rel_close(out.cpu().numpy(), want, what="served batched with hand-off")
+    bc.bc_serve_destroy(srv)
+    g.free()
+
+
 def test_serve_admission_budget(bc):
     import torch
     n, u, v = gg.rmat(13, 8, 9)

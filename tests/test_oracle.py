@@ -177,6 +177,27 @@ def test_diamond_chain_closed_form(orc):
     assert bc.tolist() == want.tolist()
 
 
+def test_wide_diamond_forest_counts(orc):
+    # From a chain's first joint, joint i lies at distance 2i with width**i shortest paths,
+    # each middle vertex of diamond i at 2i+1 with width**i, the shared sink at 2k+1 and
+    # the tail after it with width**k; vertices of other chains stay unreached.
+    copies, width, k = 3, 5, 4
+    n, u, v = gg.wide_diamond_forest(copies, width, k)
+    g = orc.Graph(n, u, v)
+    per = k * (width + 1) + 1
+    r = orc.brandes_source(g, per)   # first joint of chain 1
+    for i in range(k + 1):
+        assert r["dist"][per + i * (width + 1)] == 2 * i
+        assert r["sigma"][per + i * (width + 1)] == width ** i
+    for i in range(k):
+        for t in range(1, width + 1):
+            assert r["dist"][per + i * (width + 1) + t] == 2 * i + 1
+            assert r["sigma"][per + i * (width + 1) + t] == width ** i
+    assert r["dist"][n - 2] == 2 * k + 1 and r["sigma"][n - 2] == width ** k   # the sink
+    assert r["dist"][n - 1] == 2 * k + 2 and r["sigma"][n - 1] == width ** k   # the tail
+    assert (r["dist"][:per] == -1).all() and (r["dist"][2 * per:n - 2] == -1).all()
+
+
 # --------------------------------------------------------------------------------------
 # third-party cross-checks: scipy BFS distances, NetworkX betweenness (the paper's own
 # correctness check, section II-A)
