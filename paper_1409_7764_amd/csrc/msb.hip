@@ -147,6 +147,7 @@ template <int WG>
 struct MsbLds {
     uint32_t wsum[WG / 64];
     uint32_t off[WG];       // unit offsets of the chunk's entries
+    uint16_t own[2 * WG];   // unit -> chunk entry, for the chunk's first 2 WG units
     uint32_t ev[WG];        // entry vertex
     uint64_t em[WG];        // entry source mask
     uint32_t eb[WG];        // first out-edge
@@ -212,6 +213,19 @@ __device__ __forceinline__ uint32_t find_owner(const uint32_t* a, uint32_t p) {
         len -= half;
     }
     return lo;
+}
+
+// chunk entry of unit u: one LDS read for the first 2 WG units, a search after them
+template <int WG>
+__device__ __forceinline__ uint32_t owner_of(const MsbLds<WG>& L, uint32_t u) {
+    return u < 2 * WG ? (uint32_t)L.own[u] : find_owner<WG>(L.off, u);
+}
+
+// each entry records itself as the owner of its units (those inside the table)
+template <int WG>
+__device__ __forceinline__ void fill_owners(MsbLds<WG>& L, uint32_t off, uint32_t units) {
+    const uint32_t end = min(off + units, 2u * WG);
+    for (uint32_t q = off; q < end; ++q) L.own[q] = (uint16_t)threadIdx.x;
 }
 
 template <int WG>
@@ -490,20 +504,21 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 uint32_t units;
                 const uint32_t off = block_excl_scan<WG>((deg + 63) / 64, units, L.wsum);
                 L.off[tid] = off;
+                fill_owners<WG>(L, off, (deg + 63) / 64);
                 L.ev[tid] = v;
                 L.em[tid] = f;
                 L.eb[tid] = beg;
                 L.ed[tid] = deg;
                 __syncthreads();
                 for (uint32_t u = wave; u < units; u += 2 * NW) {   // units u and u + NW
-                    const uint32_t j = find_owner<WG>(L.off, u);
+                    const uint32_t j = owner_of<WG>(L, u);
                     const uint32_t e0 = L.eb[j] + (u - L.off[j]) * 64;
                     const uint32_t e1 = min(L.eb[j] + L.ed[j], e0 + 64);
                     const uint32_t u2 = u + NW;
                     uint32_t v2 = 0, e02 = 0, e12 = 0;
                     uint64_t f2 = 0;
                     if (u2 < units) {
-                        const uint32_t j2 = find_owner<WG>(L.off, u2);
+                        const uint32_t j2 = owner_of<WG>(L, u2);
                         v2 = L.ev[j2];
                         f2 = L.em[j2];
                         e02 = L.eb[j2] + (u2 - L.off[j2]) * 64;
@@ -572,6 +587,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     uint32_t units;
                     const uint32_t off = block_excl_scan<WG>(np, units, L.wsum);
                     L.off[tid] = off;
+                    fill_owners<WG>(L, off, np);
                     L.ev[tid] = v;
                     L.em[tid] = f;
                     L.eb[tid] = beg;
@@ -581,7 +597,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     __syncthreads();
                     for (uint32_t u = wave; u < units; u += NW) {
-                        const uint32_t j = find_owner<WG>(L.off, u);
+                        const uint32_t j = owner_of<WG>(L, u);
                         const uint32_t vj = L.ev[j];
                         const uint64_t fj = L.em[j];
                         const uint32_t dj = L.ed[j];
