@@ -423,6 +423,9 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     uint64_t* lm = a.lst_m + (size_t)team * a.cap;
     uint32_t* lvl = a.lvl + (size_t)team * (a.max_levels + 2);
     const uint32_t gtid = member * WG + tid, gthreads = W * WG;
+    // entries per chunk: large teams take smaller chunks, so the last chunks of a level (and
+    // chunks holding hubs) keep fewer members waiting at the level's barrier
+    const uint32_t CH = W >= 8 ? WG / 4 : WG;
     const uint32_t gwave = member * NW + wave, gwaves = W * NW;
     uint32_t dagc = 0;
     uint32_t n_done = 0, levels_max = 0, scans = 0;
@@ -490,12 +493,12 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             }
             for (;;) {
                 const uint32_t ch = claim_chunk(L, ctl);
-                const uint32_t c0 = lo + ch * WG;
+                const uint32_t c0 = lo + ch * CH;
                 if (c0 >= hi) break;
                 const uint32_t i = c0 + tid;
                 uint32_t v = 0, beg = 0, deg = 0;
                 uint64_t f = 0;
-                if (i < hi) {
+                if (tid < CH && i < hi) {
                     v = lv[i];
                     f = lm[i];
                     beg = a.row_ptr[v];
@@ -562,12 +565,12 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 }
                 for (;;) {
                     const uint32_t ch = claim_chunk(L, ctl);
-                    const uint32_t c0 = lo_d + ch * WG;
+                    const uint32_t c0 = lo_d + ch * CH;
                     if (c0 >= hi_d) break;
                     const uint32_t i = c0 + tid;
                     uint32_t v = 0, beg = 0, deg = 0, np = 0;
                     uint64_t f = 0;
-                    if (i < hi_d) {
+                    if (tid < CH && i < hi_d) {
                         v = lv[i];
                         f = lm[i] & ~ovf;
                         beg = a.row_ptr[v];
