@@ -23,7 +23,9 @@ bool tuning_enabled() {
 
 Knobs default_knobs(const Graph& g) {
     Knobs k;
-    k.wg_size = 256;
+    // deep graphs (lattice-like) run one source per workgroup through thousands of small
+    // levels: larger workgroups take a whole level in fewer chunks
+    k.wg_size = g.deep ? 512 : 256;
     k.team = 0;     // batched path: workgroups per batch chosen from the batch count
     k.teams = 0;
     k.hub = 64;
@@ -31,7 +33,6 @@ Knobs default_knobs(const Graph& g) {
     k.use_graph = true;
     k.batched = 0;
     k.batch_wg = 1024;
-    (void)g;
     return k;
 }
 
