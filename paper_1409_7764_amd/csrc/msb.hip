@@ -663,11 +663,9 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     if (tid == 0) L.nhub = 0;
                     __syncthreads();
                 }
-                if (!team_sync(L, ctl, W, a.stats)) {
-                    aborted = true;
-                    break;
-                }
-                for (uint32_t i = lo_n + gtid; i < hi_n; i += gthreads) mk.nxt(lv[i]) = 0ull;
+                // no clearing pass: a stale mask left in nxt[w] by a deeper level L >= d + 2
+                // never meets an entry of level d with an edge to w (such a source would
+                // reach w within d + 1), and the reset clears every listed vertex's masks
             }
         }
         if (aborted) break;
