@@ -158,6 +158,7 @@ struct MsbLds {
     unsigned long long ws[WG / 64][4];   // per wavefront: reached pairs, examined, entries, visits
     uint32_t nhub;
     uint32_t chunk;
+    uint32_t ucnt;          // next unit of the chunk to claim
     uint32_t ok;            // 0 once the team gave up on a barrier
     uint64_t ovf;           // sources flagged by this workgroup, flushed to the team at level ends
 };
@@ -374,10 +375,22 @@ __device__ __forceinline__ void finish_entry(uint32_t* sig, double* psi, double*
     }
 }
 
+// Claims `k` consecutive units of the current chunk for this wavefront (units vary in cost, so
+// wavefronts take them as they finish rather than in a fixed round-robin)
+template <int WG>
+__device__ __forceinline__ uint32_t claim_units(MsbLds<WG>& L, uint32_t k) {
+    uint32_t u = 0;
+    if (lane_id() == 0) u = atomicAdd(&L.ucnt, k);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)u);
+}
+
 // Claims the next chunk of the current phase for this workgroup (team-wide counter).
 template <int WG>
 __device__ __forceinline__ uint32_t claim_chunk(MsbLds<WG>& L, TeamCtl* c) {
-    if (threadIdx.x == 0) L.chunk = atomicAdd(&c->cc, 1u);
+    if (threadIdx.x == 0) {
+        L.chunk = atomicAdd(&c->cc, 1u);
+        L.ucnt = 0;   // every wavefront left the previous chunk's unit loop at its last barrier
+    }
     __syncthreads();
     const uint32_t ch = L.chunk;
     __syncthreads();
@@ -514,11 +527,13 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 L.eb[tid] = beg;
                 L.ed[tid] = deg;
                 __syncthreads();
-                for (uint32_t u = wave; u < units; u += 2 * NW) {   // units u and u + NW
+                for (;;) {   // units u and u + 1
+                    const uint32_t u = claim_units(L, 2u);
+                    if (u >= units) break;
                     const uint32_t j = owner_of<WG>(L, u);
                     const uint32_t e0 = L.eb[j] + (u - L.off[j]) * 64;
                     const uint32_t e1 = min(L.eb[j] + L.ed[j], e0 + 64);
-                    const uint32_t u2 = u + NW;
+                    const uint32_t u2 = u + 1;
                     uint32_t v2 = 0, e02 = 0, e12 = 0;
                     uint64_t f2 = 0;
                     if (u2 < units) {
@@ -600,7 +615,9 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     // the accumulator rows belong to this workgroup alone: workgroup scope
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     __syncthreads();
-                    for (uint32_t u = wave; u < units; u += NW) {
+                    for (;;) {
+                        const uint32_t u = claim_units(L, 1u);
+                        if (u >= units) break;
                         const uint32_t j = owner_of<WG>(L, u);
                         const uint32_t vj = L.ev[j];
                         const uint64_t fj = L.em[j];
