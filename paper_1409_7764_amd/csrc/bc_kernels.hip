@@ -38,6 +38,7 @@ namespace {
 
 constexpr uint32_t kPiece = 256;     // hub edges per wavefront work piece
 constexpr int kTpv = 4;              // thread-per-vertex mode: chunks whose largest degree is at most this
+constexpr int kIlp = 4;              // edges per thread and step in the edge-parallel modes
 constexpr double kSafeCount = 1.8e19;   // below 2^64 = 1.8447e19
 constexpr uint16_t kUnseen16 = 0xffff;
 
@@ -296,6 +297,30 @@ __device__ __forceinline__ void append_fresh(S& st, Scratch<WG>& L, bool fresh, 
     }
 }
 
+// kIlp edges per thread: every distance is read before the first claim, and every claim
+// issued before the first count update
+template <bool F64, bool SAFE, int WG, class S>
+__device__ __forceinline__ void forward_edges(S& st, Scratch<WG>& L, const bool* ok, const uint32_t* w,
+                                              const uint64_t* s, int d1, uint32_t& dag) {
+    int dw[kIlp];
+    bool fresh[kIlp];
+#pragma unroll
+    for (int t = 0; t < kIlp; ++t) dw[t] = st.dist(w[t]);
+#pragma unroll
+    for (int t = 0; t < kIlp; ++t) {
+        fresh[t] = false;
+        if (ok[t] && dw[t] < 0) dw[t] = st.claim_unseen(w[t], d1, fresh[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kIlp; ++t)
+        if (ok[t] && dw[t] == d1) {
+            ++dag;
+            add_count<F64, SAFE>(st, L, w[t], s[t]);
+        }
+#pragma unroll
+    for (int t = 0; t < kIlp; ++t) append_fresh(st, L, fresh[t], w[t]);
+}
+
 template <bool F64, bool SAFE, int WG, class S>
 __device__ __forceinline__ void forward_edge(S& st, Scratch<WG>& L, bool ok, uint32_t w, uint64_t s, int d1,
                                              uint32_t& dag) {
@@ -377,30 +402,43 @@ __device__ void expand_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__
         L.deg[tid] = deg;
         L.sig[tid] = sv;
         __syncthreads();
-        // thread per edge over the non-hub vertices of the chunk
-        for (uint32_t p0 = 0; p0 < stot; p0 += WG) {
-            const uint32_t p = p0 + tid;
-            const bool ok = p < stot;
-            uint32_t w = 0;
-            uint64_t s = 0;
-            if (ok) {
-                const uint32_t j = find_owner<WG>(L.scan, p);
-                w = col[L.beg[j] + (p - L.scan[j])];
-                s = L.sig[j];
+        // thread per edge over the non-hub vertices of the chunk, kIlp edges per thread and
+        // step (indices clamped, so every load is issued without a branch around it)
+        for (uint32_t p0 = 0; p0 < stot; p0 += kIlp * WG) {
+            uint32_t w[kIlp];
+            uint64_t s[kIlp];
+            bool ok[kIlp];
+#pragma unroll
+            for (int t = 0; t < kIlp; ++t) {
+                const uint32_t p = p0 + t * WG + tid;
+                ok[t] = p < stot;
+                const uint32_t pc = ok[t] ? p : stot - 1;
+                const uint32_t j = find_owner<WG>(L.scan, pc);
+                w[t] = col[L.beg[j] + (pc - L.scan[j])];
+                s[t] = L.sig[j];
             }
-            forward_edge<F64, SAFE>(st, L, ok, w, s, d1, dag);
+            forward_edges<F64, SAFE>(st, L, ok, w, s, d1, dag);
         }
-        // wavefront per hub piece: lanes read 64 consecutive successors per step
+        // wavefront per hub piece: lanes read 64 consecutive successors per step, kIlp steps
+        // at a time
         for (uint32_t pc = wave; pc < ptot; pc += NW) {
             const uint32_t j = find_owner<WG>(L.pscan, pc);
             const uint32_t e0 = (pc - L.pscan[j]) * kPiece;
             const uint32_t e1 = min(L.deg[j], e0 + kPiece);
             const uint32_t b = L.beg[j];
-            const uint64_t s = L.sig[j];
-            for (uint32_t e = e0; e < e1; e += 64) {
-                const bool ok = e + lane < e1;
-                const uint32_t w = ok ? col[b + e + lane] : 0u;
-                forward_edge<F64, SAFE>(st, L, ok, w, s, d1, dag);
+            const uint64_t sj = L.sig[j];
+            for (uint32_t e = e0; e < e1; e += 64 * kIlp) {
+                uint32_t w[kIlp];
+                uint64_t s[kIlp];
+                bool ok[kIlp];
+#pragma unroll
+                for (int t = 0; t < kIlp; ++t) {
+                    const uint32_t ee = e + t * 64 + lane;
+                    ok[t] = ee < e1;
+                    w[t] = col[b + (ok[t] ? ee : e1 - 1)];
+                    s[t] = sj;
+                }
+                forward_edges<F64, SAFE>(st, L, ok, w, s, d1, dag);
             }
         }
         __syncthreads();
@@ -441,13 +479,23 @@ __device__ void accumulate_level(S& st, Scratch<WG>& L, const uint32_t* __restri
             L.deg[tid] = deg;
             L.acc[tid] = 0.0;
             __syncthreads();
-            for (uint32_t p0 = 0; p0 < stot; p0 += WG) {
-                const uint32_t p = p0 + tid;
-                if (p < stot) {
-                    const uint32_t j = find_owner<WG>(L.scan, p);
-                    const double c = st.psi_if_level(col[L.beg[j] + (p - L.scan[j])], d1);
-                    if (c != 0.0) atomicAdd(&L.acc[j], c);
+            for (uint32_t p0 = 0; p0 < stot; p0 += kIlp * WG) {   // kIlp edges per thread and step
+                uint32_t w[kIlp], jj[kIlp];
+                bool ok[kIlp];
+#pragma unroll
+                for (int t = 0; t < kIlp; ++t) {
+                    const uint32_t p = p0 + t * WG + tid;
+                    ok[t] = p < stot;
+                    const uint32_t pc = ok[t] ? p : stot - 1;
+                    jj[t] = find_owner<WG>(L.scan, pc);
+                    w[t] = col[L.beg[jj[t]] + (pc - L.scan[jj[t]])];
                 }
+                double c[kIlp];
+#pragma unroll
+                for (int t = 0; t < kIlp; ++t) c[t] = st.psi_if_level(w[t], d1);
+#pragma unroll
+                for (int t = 0; t < kIlp; ++t)
+                    if (ok[t] && c[t] != 0.0) atomicAdd(&L.acc[jj[t]], c[t]);
             }
             for (uint32_t pc = wave; pc < ptot; pc += NW) {
                 const uint32_t j = find_owner<WG>(L.pscan, pc);
@@ -455,7 +503,22 @@ __device__ void accumulate_level(S& st, Scratch<WG>& L, const uint32_t* __restri
                 const uint32_t e1 = min(L.deg[j], e0 + kPiece);
                 const uint32_t b = L.beg[j];
                 double part = 0.0;
-                for (uint32_t e = e0 + lane; e < e1; e += 64) part += st.psi_if_level(col[b + e], d1);
+                for (uint32_t e = e0; e < e1; e += 64 * kIlp) {
+                    uint32_t w[kIlp];
+                    bool ok[kIlp];
+#pragma unroll
+                    for (int t = 0; t < kIlp; ++t) {
+                        const uint32_t ee = e + t * 64 + lane;
+                        ok[t] = ee < e1;
+                        w[t] = col[b + (ok[t] ? ee : e1 - 1)];
+                    }
+                    double c[kIlp];
+#pragma unroll
+                    for (int t = 0; t < kIlp; ++t) c[t] = st.psi_if_level(w[t], d1);
+#pragma unroll
+                    for (int t = 0; t < kIlp; ++t)
+                        if (ok[t]) part += c[t];
+                }
                 part = wave_sum(part);
                 if (lane == 0 && part != 0.0) atomicAdd(&L.acc[j], part);
             }
