@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 def algorithmic_bytes(info, n):
     """Bytes the launch's design must move, from its exact work counters.
 
-    One source per workgroup (paths 0, 1): 96 B per reached vertex, 16 B per examined edge,
+    One source per workgroup (paths 0, 1, 3): 96 B per reached vertex, 16 B per examined edge,
     24 B per shortest-path DAG edge, summed over sources.
     64-source batches (path 2): 144 B per level-list entry, 24 B per out-edge read for an
     entry (forward + backward), 20 B per reached (vertex, source) pair (32-bit count read in
@@ -179,7 +179,7 @@ def bench_single(args, torch, bcmi, gg):
         "config": cfg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ["k_bc_global", "k_bc_lds", "k_msb"][inf["path"]],
+                     "kernel": ["k_bc_global", "k_bc_lds", "k_msb", "k_bc_narrow"][inf["path"]],
                      "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": nbytes},
         "extra": {
             "traversed_gteps": inf["examined"] / (ms_per_step / 1e3) / 1e9,
@@ -187,9 +187,9 @@ def bench_single(args, torch, bcmi, gg):
             "sources": k, "reached": inf["reached"], "examined": inf["examined"],
             "dag_edges": inf["dag_edges"], "levels_max": inf["levels_max"],
             "sigma_fp64_fallback_sources": inf["n_sigma_fp64_fallback"],
-            "path": ["global", "lds", "batched"][inf["path"]], "tuning": tune,
+            "path": ["global", "lds", "batched", "narrow"][inf["path"]], "tuning": tune,
             "batch_entries": inf["batch_entries"], "batch_edge_visits": inf["batch_edge_visits"],
-            "batch_scans": inf["batch_scans"],
+            "batch_scans": inf["batch_scans"], "batch_handoffs": inf["batch_handoffs"],
             # the per-source accounting 16|E_s| + 32|D_s| + 92|R_s| summed over sources, whatever
             # the path: what one source at a time would move (batches share their edge reads)
             "per_source_convention_gbs": (16 * inf["examined"] + 32 * inf["dag_edges"] + 92 * inf["reached"])

@@ -69,7 +69,9 @@ typedef struct {
     int32_t lds_max_n;          /* largest n run by the LDS-resident path; < 0 = never */
     int32_t use_graph;          /* 1 = replay a captured hipGraph, -1 = plain launches */
     int32_t batched;            /* 1 = 64 sources per batch (one per wavefront lane),
-                                   -1 = one source per workgroup */
+                                   -1 = one source per workgroup,
+                                   2 = one source per workgroup with each level held in LDS
+                                       (switched off: BC_E_INVAL) */
     int32_t batch_wg_size;      /* workgroup size of the batched kernel: 256, 512, 1024 */
 } bc_tuning;
 
@@ -79,7 +81,8 @@ typedef struct {
     uint32_t levels_max;            /* deepest BFS (number of levels) over the sources */
     uint32_t path;                  /* 0 = one source per workgroup, state in global memory;
                                        1 = one source per workgroup, state in LDS;
-                                       2 = 64-source batches */
+                                       2 = 64-source batches;
+                                       3 = one source per workgroup, levels in LDS */
     double kernel_ms;               /* device time of the call (HIP events) */
     double t_submit_ms, t_start_ms, t_done_ms; /* bc_serve_poll only: server clock */
     uint64_t reached;               /* sum over sources of vertices reached (source included) */
@@ -88,8 +91,10 @@ typedef struct {
     uint64_t batch_entries;         /* path 2: (vertex, level) entries of the batches' lists */
     uint64_t batch_edge_visits;     /* path 2: out-edges of those entries */
     uint64_t batch_scans;           /* path 2: level-collect passes (each reads every vertex's masks) */
-    uint64_t batch_handoffs;        /* path 2: sources handed to the one-source-per-workgroup kernel
-                                       (32-bit count cap, list capacity or level cap) */
+    uint64_t batch_handoffs;        /* paths 2, 3: sources handed to the one-source-per-workgroup
+                                       kernel with state in global memory (path 2: 32-bit count cap,
+                                       list capacity or level cap; path 3: a level wider than the
+                                       LDS tables) */
     uint64_t batch_cycles[3];       /* path 2: workgroup clock cycles summed over workgroups, in the
                                        forward sweep, the backward sweep, and state reset */
 } bc_info;

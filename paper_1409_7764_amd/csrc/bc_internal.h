@@ -61,7 +61,7 @@ struct CallStats {
     uint32_t bad_source;     // sources with id >= n (skipped)
     uint32_t work_head2;     // work counter of a follow-up launch in the same call
     uint32_t aborted;        // a batched team gave up waiting at a barrier
-    uint32_t handoffs;       // batched path: sources handed to the per-source kernel
+    uint32_t handoffs;       // batched and narrow paths: sources handed to the global-memory kernel
     uint64_t reached;        // sum over sources of reached vertices (source included)
     uint64_t examined;       // sum over sources of out-edges of reached vertices
     uint64_t dag_edges;      // sum over sources of shortest-path DAG edges
@@ -79,7 +79,8 @@ struct Knobs {
     int hub = 32;                // wavefront-per-vertex threshold
     int lds_max_n = 4096;
     bool use_graph = true;
-    int batched = 0;             // 1: 64-source batches, -1: one source per workgroup, 0: auto
+    int batched = 0;             // 1: 64-source batches, -1: one source per workgroup, 2: one source per
+                                 // workgroup with its levels in LDS, 0: auto
     int batch_wg = 1024;         // workgroup size of the batched kernel
 };
 
@@ -146,7 +147,7 @@ struct RunArgs {
     double* ex_delta = nullptr;
 };
 // Enqueue a full BC pass over the given sources on `stream` (zeroes bc first).  Returns
-// which path ran (0 global slots, 1 LDS).
+// which path ran (0 global slots, 1 LDS, 2 batched, 3 levels in LDS).
 int run_sources(const RunArgs& a, const Knobs& k, hipStream_t stream, Graph& g);
 void read_stats(Graph& g, hipStream_t stream, CallStats* out);
 
@@ -226,6 +227,16 @@ size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels);
 using RetryLaunch = void (*)(void*, const uint32_t*, const uint32_t*, uint32_t, bool, hipStream_t);
 void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
                      int wg, int team_knob, int slots_cap, hipStream_t st, RetryLaunch retry_launch, void* retry_ctx);
+
+// ---- one source per workgroup, levels in LDS (narrow.hip) ---------------------------------
+struct NarrowPool;
+NarrowPool* narrow_pool_new();
+void narrow_pool_delete(NarrowPool* p);
+size_t narrow_slot_bytes(uint32_t n);
+// sources given in caller numbering (null: item i is source i); sources whose levels outgrow
+// the LDS tables are handed to `retry_launch` with caller ids
+void run_narrow_enqueue(NarrowPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc,
+                        CallStats* stats, int slots_cap, hipStream_t st, RetryLaunch retry_launch, void* retry_ctx);
 
 // ---- tuning (tune.hip) -------------------------------------------------------------------
 Knobs resolve_knobs(Graph& g, const bc_tuning* t);

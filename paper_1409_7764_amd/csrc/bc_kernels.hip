@@ -923,6 +923,7 @@ struct GraphScratch {
     WorkDesc* desc = nullptr;    // device, one descriptor
     WorkDesc* rdesc = nullptr;   // device, descriptor of the retry list
     MsbPool* msb = nullptr;
+    NarrowPool* narrow = nullptr;
 };
 
 static GraphScratch& scratch_of(Graph& g) {
@@ -937,6 +938,7 @@ void graph_scratch_free(Graph& g) {
     if (s->desc) (void)hipFree(s->desc);
     if (s->rdesc) (void)hipFree(s->rdesc);
     msb_pool_delete(s->msb);
+    narrow_pool_delete(s->narrow);
     delete s;
     g.slots = nullptr;
 }
@@ -994,21 +996,31 @@ static void retry_launch(void* ctx, const uint32_t* list, const uint32_t* count,
 }
 
 int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g);
+int run_narrow(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g);
 
 // Automatic choice: the batched kernel for graphs beyond the LDS path with at least one full
 // batch of sources, unless the graph is deep (most of it lies beyond the batching order's
 // ranked levels): a batch then runs past the kernel's level cap and goes to the per-source
 // kernel anyway.
 static bool want_batched(const Knobs& k, const Graph& g, uint32_t items) {
-    if (k.batched < 0) return false;
+    if (k.batched < 0 || k.batched == 2) return false;
     const bool lds_ok = k.lds_max_n > 0 && g.n <= k.lds_max_n;
     if (k.batched > 0) return true;
     return !lds_ok && items >= 64 && !g.deep;
 }
 
+// The levels-in-LDS kernel (narrow.hip) is switched off: its first device run faulted and the
+// cause is not yet known.  Asking for it is an error; deep graphs keep the global-memory
+// kernel.
+static bool want_narrow(const Knobs& k, const Graph&) {
+    BC_REQUIRE(k.batched != 2, BC_E_INVAL, "the levels-in-LDS path (batched = 2) is switched off");
+    return false;
+}
+
 int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     GraphScratch& gs = scratch_of(g);
     const bool exporting = ra.ex_dist || ra.ex_sigma || ra.ex_sigma_f || ra.ex_delta;
+    if (!exporting && want_narrow(k, g)) return run_narrow(ra, k, st, g);
     if (!exporting && want_batched(k, g, ra.num_items)) return run_batched(ra, k, st, g);
     if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
     if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
@@ -1077,6 +1089,30 @@ int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     return 2;
 }
 
+int run_narrow(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
+    GraphScratch& gs = scratch_of(g);
+    if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
+    if (!gs.rdesc) BC_HIP_TRY(hipMalloc((void**)&gs.rdesc, sizeof(WorkDesc)));
+    if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
+    if (!gs.narrow) gs.narrow = narrow_pool_new();
+    WorkDesc d{};
+    d.bc = ra.bc;
+    d.n = g.n;
+    d.num_items = ra.num_items;
+    BC_HIP_TRY(hipMemcpyAsync(gs.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    // zero BC and the call counters
+    LaunchPlan z;
+    z.args.descs = gs.desc;
+    z.args.ndesc = 1;
+    z.args.total_items = 0;
+    z.args.stats = g.stats;
+    z.args.zero_outputs = 1;
+    z.grid = 0;
+    enqueue_plan(z, st, (uint32_t)g.n);
+    RetryCtx rc{&g, &gs, k, ra.bc};
+    run_narrow_enqueue(*gs.narrow, g, ra.sources, ra.num_items, ra.bc, g.stats, k.teams, st, retry_launch, &rc);
+    return 3;
+}
 
 // Drops the batched path's state after a team gave up on a barrier (the state is dirty).
 void graph_discard_batched_state(Graph& g) {

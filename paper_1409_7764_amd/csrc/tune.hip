@@ -116,7 +116,10 @@ Knobs resolve_knobs(Graph& g, const bc_tuning* t) {
     if (t->hub_threshold) k.hub = t->hub_threshold;
     if (t->lds_max_n) k.lds_max_n = t->lds_max_n;
     if (t->use_graph) k.use_graph = t->use_graph > 0;
-    if (t->batched) k.batched = t->batched;
+    if (t->batched) {
+        BC_REQUIRE(t->batched >= -1 && t->batched <= 2, BC_E_INVAL, "batched must be -1, 0, 1 or 2");
+        k.batched = t->batched;
+    }
     if (t->batch_wg_size) {
         BC_REQUIRE(t->batch_wg_size == 256 || t->batch_wg_size == 512 || t->batch_wg_size == 1024, BC_E_INVAL,
                    "batch_wg_size must be 256, 512 or 1024");
