@@ -5,7 +5,8 @@
 //             and successor w: the first visitor claims w for level d+1 (compare-and-swap on
 //             its distance) and appends it to the next frontier; every edge with
 //             dist[w] = d+1 adds sigma[v] into sigma[w] (64-bit integer atomics; a carry out
-//             of bit 63 flags the source, which is then recounted in double precision).
+//             of bit 63 flags the source: its finished levels are converted to double
+//             precision and the level being counted is recounted in double precision).
 //   backward: levels from the deepest to 0.  Each vertex v of level d owns its own update,
 //             pulling from its successors w (dist[w] = d+1):
 //                 delta[v] = sigma[v] * sum_w psi[w],   psi[w] = (1 + delta[w]) / sigma[w]
@@ -545,56 +546,59 @@ __device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s,
     uint32_t count = 0;
     int nlev = 0;
     uint32_t exam = 0, dag = 0;
-    for (;;) {   // exact 64-bit counts first; a second pass in double precision after a carry
-        exam = 0;
-        dag = 0;
-        if (tid == 0) {
-            st.seed(s, f64 ? d2u(1.0) : 1ull);
-            L.tail = 1;
-            L.ovf = 0;
-            L.msig = 0;
-        }
-        uint64_t msig_prev = 1;   // level 0 holds the source, count 1
-        const double maxin2 = (double)D.max_in * (double)D.max_in;
-        st.barrier();
-        uint32_t lo = 0, hi = 1;
-        int d = 0;
-        bool overflowed = false;
-        for (;;) {
-            // no carry can occur this level if (largest count on level d-1) * maxin^2 < 2^64
-            const bool safe = d == 0 || (D.max_in && (double)msig_prev * maxin2 < kSafeCount);
-            if (f64)
-                expand_level<true, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
-            else if (safe)
-                expand_level<false, true, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
-            else
-                expand_level<false, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
-            st.barrier();
-            const uint32_t tail = L.tail;
-            const bool ov = L.ovf != 0u;
-            msig_prev = L.msig;
-            __syncthreads();
-            if (tid == 0) L.msig = 0;   // ordered before the next level's updates by its first barrier
-            if (!f64 && ov) {
-                overflowed = true;
-                count = tail;
-                break;
-            }
-            if (tail == hi) {
-                count = tail;
-                break;
-            }
-            if (tid == 0) st.set_level_end(d + 1, tail);
-            lo = hi;
-            hi = tail;
-            ++d;
-        }
-        nlev = d + 1;
-        if (!overflowed) break;
-        for (uint32_t i = tid; i < count; i += WG) st.reset(st.q(i));
-        st.barrier();
-        f64 = true;
+    if (tid == 0) {
+        st.seed(s, 1ull);
+        L.tail = 1;
+        L.ovf = 0;
+        L.msig = 0;
     }
+    uint64_t msig_prev = 1;   // level 0 holds the source, count 1
+    const double maxin2 = (double)D.max_in * (double)D.max_in;
+    st.barrier();
+    uint32_t lo = 0, hi = 1;
+    int d = 0;
+    for (;;) {
+        // no carry can occur this level if (largest count on level d-1) * maxin^2 < 2^64
+        const bool safe = d == 0 || (D.max_in && (double)msig_prev * maxin2 < kSafeCount);
+        if (f64)
+            expand_level<true, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+        else if (safe)
+            expand_level<false, true, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+        else
+            expand_level<false, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+        st.barrier();
+        const uint32_t tail = L.tail;
+        const bool ov = L.ovf != 0u;
+        msig_prev = L.msig;
+        __syncthreads();
+        if (tid == 0) L.msig = 0;   // ordered before the next level's updates by its first barrier
+        if (!f64 && ov) {
+            // A 64-bit sum carried while level d+1 was counted.  Levels 0..d are final and exact:
+            // they become doubles; level d+1's partial sums are dropped and recounted in double
+            // precision from level d (every vertex of level d+1 is already claimed, so the
+            // recount appends nothing; its edges are not counted twice).
+            for (uint32_t i = tid; i < hi; i += WG) {
+                const uint32_t v = st.q(i);
+                st.set_val(v, d2u((double)st.val(v)));
+            }
+            for (uint32_t i = hi + tid; i < tail; i += WG) st.set_val(st.q(i), 0ull);
+            if (tid == 0) L.ovf = 0;
+            st.barrier();
+            f64 = true;
+            uint32_t exam2 = 0, dag2 = 0;
+            expand_level<true, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam2, dag2);
+            st.barrier();
+        }
+        if (tail == hi) {
+            count = tail;
+            break;
+        }
+        if (tid == 0) st.set_level_end(d + 1, tail);
+        lo = hi;
+        hi = tail;
+        ++d;
+    }
+    nlev = d + 1;
     if (a.ex_dist || a.ex_sigma || a.ex_sigma_f) {   // inspection: the forward sweep's result
         for (uint32_t i = tid; i < count; i += WG) {
             const uint32_t v = st.q(i);
@@ -605,9 +609,9 @@ __device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s,
             if (a.ex_sigma_f) a.ex_sigma_f[out] = f64 ? u2d(x) : (double)x;
         }
     }
-    uint32_t hi = count;
+    hi = count;
     for (int dd = nlev - 1; dd >= 0; --dd) {
-        const uint32_t lo = st.level_begin(dd, hi);
+        lo = st.level_begin(dd, hi);
         if (f64)
             accumulate_level<true, WG>(st, L, D.row_ptr, D.col, lo, hi, dd, a.hub, a.tpv_max, s, D.bc, a.ex_delta,
                                        D.iperm);
@@ -1024,13 +1028,16 @@ int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     if (!exporting && want_batched(k, g, ra.num_items)) return run_batched(ra, k, st, g);
     if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
     if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
+    // Deep graphs keep the caller's numbering: a lattice-like graph's own ids put a frontier's
+    // neighbours in shared cache lines, which the in-degree relabelling would scatter.
+    const bool own_ids = g.deep;
     WorkDesc d{};
-    d.row_ptr = g.krow();
-    d.col = g.kcol();
+    d.row_ptr = own_ids ? g.row_ptr : g.krow();
+    d.col = own_ids ? g.col : g.kcol();
     d.bc = ra.bc;
     d.sources = ra.sources;
-    d.perm = g.perm;
-    d.iperm = g.iperm;
+    d.perm = own_ids ? nullptr : g.perm;
+    d.iperm = own_ids ? nullptr : g.iperm;
     d.counters = nullptr;
     d.n = g.n;
     d.max_in = g.max_in_degree;

@@ -374,6 +374,27 @@ def test_narrow_is_automatic_for_deep_graphs(bc):
     g.free()
 
 
+def test_deep_graph_caller_numbering(bc):
+    """A deep graph above the relabelling size runs the global-memory kernel on the caller's
+    own numbering (the automatic choice); results and work counters match the oracle."""
+    n, u, v = gg.grid_random_orientation(131, 129, 8)
+    g = bc.bc_build_csr(n, u, v)
+    S = np.concatenate([gg.uniform_sources(n, 150, 12), np.array([7, 7], np.uint32)])
+    want, ovf, st = oracle.bc(oracle.Graph(n, u, v), S)
+    say("deep graph, n", n)
+    got, info = bc.bc_sampled(g, S, info=True)
+    assert info["path"] == 0
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    assert info["levels_max"] == int(st[:, 3].max())
+    rel_close(np_of(got), want)
+    for s in [0, 7, n - 1]:
+        r = bc.bc_sssp(g, s)
+        w = oracle.brandes_source(oracle.Graph(n, u, v), s)
+        assert np.array_equal(np_of(r["dist"]), w["dist"])
+        assert np.array_equal(np_of(r["sigma_u64"]).view(np.uint64), w["sigma"])
+    g.free()
+
+
 def test_narrow_request_is_rejected(bc):
     n, u, v = gg.grid_random_orientation(20, 20, 5)
     g = bc.bc_build_csr(n, u, v)
