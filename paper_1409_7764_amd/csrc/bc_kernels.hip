@@ -85,6 +85,8 @@ struct Scratch {
     uint32_t deg[WG];
     uint64_t sig[WG];
     double acc[WG];
+    uint32_t nq[WG];           // global-memory state: the first WG vertices appended this level
+    uint32_t nq_base;          // queue position of nq[0] (the next level's first entry)
     uint32_t tail;             // next free queue position
     uint32_t ovf;              // a 64-bit count carried
     unsigned long long msig;   // largest count of the level being expanded
@@ -138,6 +140,8 @@ __device__ __forceinline__ void classify_chunk(Scratch<WG>& L, uint32_t deg, boo
 
 // ---- per-source state policies ------------------------------------------------------------
 struct GState {
+    static constexpr bool kLdsList = true;       // keep a small next level's vertex list in LDS too
+    static constexpr bool kDirectClaim = true;   // thread-per-vertex mode claims without a distance read
     VRec* rec;
     uint32_t* queue;
     uint32_t* lvl;
@@ -207,6 +211,8 @@ struct GState {
 };
 
 struct LState {
+    static constexpr bool kLdsList = false;      // the queue itself is in LDS
+    static constexpr bool kDirectClaim = false;  // distance reads are LDS reads
     uint16_t* dist16;   // 0xffff = not reached
     uint64_t* vals;
     uint16_t* queue;
@@ -294,7 +300,11 @@ __device__ __forceinline__ void append_fresh(S& st, Scratch<WG>& L, bool fresh, 
         uint32_t base = 0;
         if (lane == leader) base = atomicAdd(&L.tail, (uint32_t)__builtin_popcountll(mask));
         base = __shfl(base, leader, 64);
-        if (fresh) st.q_set(base + (uint32_t)__builtin_popcountll(mask & lanemask_lt()), w);
+        if (fresh) {
+            const uint32_t pos = base + (uint32_t)__builtin_popcountll(mask & lanemask_lt());
+            st.q_set(pos, w);
+            if (S::kLdsList && pos - L.nq_base < (uint32_t)WG) L.nq[pos - L.nq_base] = w;
+        }
     }
 }
 
@@ -323,46 +333,28 @@ __device__ __forceinline__ void forward_edges(S& st, Scratch<WG>& L, const bool*
 }
 
 template <bool F64, bool SAFE, int WG, class S>
-__device__ __forceinline__ void forward_edge(S& st, Scratch<WG>& L, bool ok, uint32_t w, uint64_t s, int d1,
-                                             uint32_t& dag) {
-    bool fresh = false;
-    if (ok) {
-        const int dw = st.claim(w, d1, fresh);
-        if (dw == d1) {
-            ++dag;
-            add_count<F64, SAFE>(st, L, w, s);
-        }
-    }
-    const uint64_t mask = __ballot(fresh);
-    if (mask) {
-        const unsigned lane = lane_id();
-        const unsigned leader = __builtin_ctzll(mask);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&L.tail, (uint32_t)__builtin_popcountll(mask));
-        base = __shfl(base, leader, 64);
-        if (fresh) st.q_set(base + (uint32_t)__builtin_popcountll(mask & lanemask_lt()), w);
-    }
-}
-
-template <bool F64, bool SAFE, int WG, class S>
 __device__ void expand_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__ row_ptr,
                              const uint32_t* __restrict__ col, uint32_t lo, uint32_t hi, int d, uint32_t hub,
-                             uint32_t tpv_max, uint32_t& exam, uint32_t& dag) {
+                             uint32_t tpv_max, bool lds_list, uint32_t& exam, uint32_t& dag) {
     const unsigned tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
     constexpr unsigned NW = WG / 64;
     const int d1 = d + 1;
+    // a level of at most WG vertices was also listed in LDS by the level before (lds_list);
+    // its entries are read before the chunk's first barrier, and this level's appends (which
+    // rewrite the LDS list) come after it
     for (uint32_t c0 = lo; c0 < hi; c0 += WG) {
         const uint32_t i = c0 + tid;
         const bool valid = i < hi;
         uint32_t v = 0, beg = 0, deg = 0;
         uint64_t sv = 0;
         if (valid) {
-            v = st.q(i);
+            v = lds_list ? L.nq[i - lo] : st.q(i);
             beg = row_ptr[v];
             deg = row_ptr[v + 1] - beg;
             sv = st.val(v);
             exam += deg;
         }
+        if (S::kLdsList && tid == 0) L.nq_base = hi;
         const bool is_hub = valid && deg >= hub;
         uint32_t so, stot, po, ptot, mx;
         classify_chunk<WG>(L, deg, is_hub, so, stot, po, ptot, mx);
@@ -379,12 +371,21 @@ __device__ void expand_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__
             bool fresh[kTpv];
 #pragma unroll
             for (int t = 0; t < kTpv; ++t) w[t] = (uint32_t)t < my ? col[beg + t] : 0u;
+            if (S::kDirectClaim) {
+                // the compare-and-swap returns the distance a plain read would: one round trip
 #pragma unroll
-            for (int t = 0; t < kTpv; ++t) dw[t] = (uint32_t)t < my ? st.dist(w[t]) : 0;
+                for (int t = 0; t < kTpv; ++t) {
+                    fresh[t] = false;
+                    dw[t] = (uint32_t)t < my ? st.claim_unseen(w[t], d1, fresh[t]) : 0;
+                }
+            } else {
 #pragma unroll
-            for (int t = 0; t < kTpv; ++t) {
-                fresh[t] = false;
-                if ((uint32_t)t < my && dw[t] < 0) dw[t] = st.claim_unseen(w[t], d1, fresh[t]);
+                for (int t = 0; t < kTpv; ++t) dw[t] = (uint32_t)t < my ? st.dist(w[t]) : 0;
+#pragma unroll
+                for (int t = 0; t < kTpv; ++t) {
+                    fresh[t] = false;
+                    if ((uint32_t)t < my && dw[t] < 0) dw[t] = st.claim_unseen(w[t], d1, fresh[t]);
+                }
             }
 #pragma unroll
             for (int t = 0; t < kTpv; ++t)
@@ -557,15 +558,17 @@ __device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s,
     st.barrier();
     uint32_t lo = 0, hi = 1;
     int d = 0;
+    bool lds_list = false;   // this level's vertices are also listed in L.nq
     for (;;) {
         // no carry can occur this level if (largest count on level d-1) * maxin^2 < 2^64
         const bool safe = d == 0 || (D.max_in && (double)msig_prev * maxin2 < kSafeCount);
         if (f64)
-            expand_level<true, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+            expand_level<true, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, lds_list, exam, dag);
         else if (safe)
-            expand_level<false, true, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+            expand_level<false, true, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, lds_list, exam, dag);
         else
-            expand_level<false, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam, dag);
+            expand_level<false, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, lds_list, exam,
+                                           dag);
         st.barrier();
         const uint32_t tail = L.tail;
         const bool ov = L.ovf != 0u;
@@ -586,7 +589,8 @@ __device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s,
             st.barrier();
             f64 = true;
             uint32_t exam2 = 0, dag2 = 0;
-            expand_level<true, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, exam2, dag2);
+            // level d's list in LDS was overwritten by level d+1's: read the queue
+            expand_level<true, false, WG>(st, L, D.row_ptr, D.col, lo, hi, d, a.hub, a.tpv_max, false, exam2, dag2);
             st.barrier();
         }
         if (tail == hi) {
@@ -594,6 +598,7 @@ __device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s,
             break;
         }
         if (tid == 0) st.set_level_end(d + 1, tail);
+        lds_list = S::kLdsList && tail - hi <= (uint32_t)WG;   // every entry of level d+1 went to L.nq
         lo = hi;
         hi = tail;
         ++d;
