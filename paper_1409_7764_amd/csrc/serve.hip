@@ -262,7 +262,10 @@ struct Server {
         for (int c = 0; c < 2; ++c) {
             if (cls[c].empty()) continue;
             Knobs k = knobs;
-            if (c == 1) {
+            if (c == 0) {   // LDS-resident graphs: the single-graph defaults for that path
+                k.wg_size = 512;
+                k.hub = 128;
+            } else {
                 k.lds_max_n = -1;
                 k.teams = max_slots;
             }
@@ -505,7 +508,9 @@ bc_status bc_serve_submit(bc_server sh, bc_graph gh, const uint32_t* h_sources, 
             for (uint32_t x : r.h_sources) BC_REQUIRE(x < (uint32_t)g->n, BC_E_RANGE, "source id >= n");
         }
         r.d_bc = d_bc;
-        r.lds = lds_fits(s->knobs, (uint32_t)g->n, s->device);
+        Knobs lds_knobs = s->knobs;
+        lds_knobs.wg_size = 512;
+        r.lds = lds_fits(lds_knobs, (uint32_t)g->n, s->device);
         // larger shallow graphs with at least one full batch of sources: 64 per wavefront
         r.batched = !r.lds && g->order && !g->deep && r.k >= 64 && s->knobs.batched >= 0;
         r.footprint = s->footprint(*g, r.k, r.lds, r.batched);
