@@ -58,10 +58,12 @@ struct Chunk {
 
 constexpr uint32_t kChunkGlobal = 64;     // sources per chunk on the global-slot path
 constexpr uint32_t kChunkLds = 1024;      // sources per chunk on the LDS-resident path
-constexpr uint32_t kChunkBatched = 1024;  // sources per chunk on the batched path (16 batches)
+constexpr uint32_t kChunkBatched = 16384;  // sources per chunk on the batched path (256 batches:
+                                           // a launch carries ~1 ms of level-barrier latency, so
+                                           // 1,024-source chunks ran at a third of the rate)
 constexpr uint32_t kTickDescs = 4096;     // chunks per tick
-constexpr uint32_t kTickBatched = 8;      // batched chunks per tick
-constexpr int kServeTeams = 32;           // state slots of the batched path
+constexpr uint32_t kTickBatched = 1;      // batched chunks per tick
+constexpr int kServeTeams = 64;           // state slots of the batched path
 
 struct Tick {
     bool busy = false;

@@ -46,7 +46,7 @@ def footprint(n, m, k, path):
     if path == "global":
         f += min(k, 64) * (24 * n + 4)
     elif path == "batched":
-        f += min((k + 63) // 64, 32) * msb_team_bytes(n)
+        f += min((k + 63) // 64, 64) * msb_team_bytes(n)
     return f
 
 
@@ -105,7 +105,7 @@ def test_serve_overlap_and_continuous_batching(bc):
     srv = bc.bc_serve_create(64 << 30)
     out_a = torch.empty(big.n, dtype=torch.float64, device="cuda")
     out_b = torch.empty(small.n, dtype=torch.float64, device="cuda")
-    SA = gg.uniform_sources(big.n, 8192, 1)
+    SA = gg.uniform_sources(big.n, big.n, 1)
     ta = bc.bc_serve_submit(srv, big, SA, out_a)   # spans many ticks
     time.sleep(0.005)
     tb = bc.bc_serve_submit(srv, small, None, out_b)
