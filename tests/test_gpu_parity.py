@@ -299,6 +299,28 @@ def test_overflow_grid_dag(bc):
     g.free()
 
 
+@pytest.mark.parametrize("side", [40, 70])
+def test_overflow_counts_against_exact_binomials(bc, side):
+    """A count carry mid-search: the finished levels continue in double precision.  From the
+    corner of a monotone grid DAG, sigma(i, j) = C(i+j, i) exactly; the reported FP64 counts
+    must match the exact binomials well inside 1e-9 (40x40 runs the LDS-resident kernel,
+    70x70 the global-memory one), distances exactly, dependencies the oracle's."""
+    from math import comb
+    n, u, v = gg.grid_dag(side, side)
+    g = bc.bc_build_csr(n, u, v)
+    say("grid dag exact binomials", side)
+    r = bc.bc_sssp(g, 0)
+    assert r["overflow"]
+    i, j = np.divmod(np.arange(n), side)
+    assert np.array_equal(np_of(r["dist"]), i + j)
+    exact = np.array([float(comb(int(a + b), int(a))) for a, b in zip(i, j)])
+    got = np_of(r["sigma_f64"])
+    assert np.max(np.abs(got - exact) / exact) <= 1e-12
+    w = oracle.brandes_source(oracle.Graph(n, u, v), 0)
+    rel_close(np_of(r["delta"]), w["delta"], what="delta")
+    g.free()
+
+
 def test_high_diameter_lattice(bc):
     n, u, v = gg.grid_random_orientation(64, 64, 1)
     g = bc.bc_build_csr(n, u, v)
