@@ -82,7 +82,8 @@ typedef struct {
     uint32_t path;                  /* 0 = one source per workgroup, state in global memory;
                                        1 = one source per workgroup, state in LDS;
                                        2 = 64-source batches;
-                                       3 = one source per workgroup, levels in LDS */
+                                       3 = one source per workgroup, levels in LDS;
+                                       4, 5, 6 = bc_paper_strategy 1, 2, 3 */
     double kernel_ms;               /* device time of the call (HIP events) */
     double t_submit_ms, t_start_ms, t_done_ms; /* bc_serve_poll only: server clock */
     uint64_t reached;               /* sum over sources of vertices reached (source included) */
@@ -156,6 +157,23 @@ BC_API bc_status bc_batch(const bc_graph* gs, int32_t num_graphs, double* const*
 /* Autotune the launch knobs for this graph (times candidate configurations on a sample of
  * sources; cached per device and graph class).  Synchronous. */
 BC_API bc_status bc_tune(bc_graph g, bc_tuning* out);
+
+/* The three GPU strategies compared in the paper (section I, section III), rebuilt as baselines
+ * for rerunning that comparison on its own workload (BA digraphs); not the fast path:
+ *   strategy 1: one workgroup per source, vertex-parallel levels (every vertex tested each
+ *               level, a vertex's successors walked by one thread);
+ *   strategy 2: one workgroup per source, edge-parallel levels over the edge list;
+ *   strategy 3: one source at a time over the whole grid, one launch per level, the host
+ *               reading an "another level?" flag after each forward launch.
+ * wg_size: threads per workgroup, multiple of 64 in [64, 1024] (the paper's block-size study).
+ * d_sources: k device source ids (multiset, raw sum; NULL allowed when k = 0); k < 0 = all n
+ * vertices (exact BC).
+ * d_bc: n doubles, overwritten with the same BC as bc_exact / bc_sampled (sigma is held in
+ * double precision here, exact below 2^53).  info (nullable): n_sources, levels_max,
+ * kernel_ms, path = 3 + strategy.  Errors: BC_E_INVAL (strategy, wg_size, null output),
+ * BC_E_RANGE (a source id >= n), BC_E_NOMEM, BC_E_HIP.  Returns after the work is done. */
+BC_API bc_status bc_paper_strategy(bc_graph g, int32_t strategy, int32_t wg_size, const uint32_t* d_sources,
+                                   int32_t k, double* d_bc, void* stream, bc_info* info);
 
 /* ---- serving ------------------------------------------------------------------------
  * A server owns a device stream and a host thread.  Requests are admitted while the sum

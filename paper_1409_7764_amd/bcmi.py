@@ -73,14 +73,16 @@ def lib():
         L.bc_batch.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(bc_tuning), P,
                                ctypes.POINTER(bc_info)]
         L.bc_tune.argtypes = [P, ctypes.POINTER(bc_tuning)]
+        L.bc_paper_strategy.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P, P,
+                                        ctypes.POINTER(bc_info)]
         L.bc_serve_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(P)]
         L.bc_serve_submit.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_uint64)]
         L.bc_serve_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(bc_info)]
         L.bc_serve_destroy.argtypes = [P]
         for name in ["bc_build_csr", "bc_graph_info", "bc_graph_arrays", "bc_graph_order", "bc_graph_free", "bc_exact",
                      "bc_sampled",
-                     "bc_sssp", "bc_batch", "bc_tune", "bc_serve_create", "bc_serve_submit", "bc_serve_poll",
-                     "bc_serve_destroy"]:
+                     "bc_sssp", "bc_batch", "bc_tune", "bc_paper_strategy", "bc_serve_create", "bc_serve_submit",
+                     "bc_serve_poll", "bc_serve_destroy"]:
             getattr(L, name).restype = ctypes.c_int32
         L.bc_last_error.restype = ctypes.c_char_p
         L.bc_version.restype = ctypes.c_char_p
@@ -215,6 +217,20 @@ def bc_sampled(g: Graph, sources, out=None, tuning=None, stream=None, info=False
     if not info:
         # keep the source tensor alive until the stream has consumed it
         _check_keepalive(srcs, stream)
+    return (out, inf.as_dict()) if info else out
+
+
+def bc_paper_strategy(g: Graph, strategy: int, wg_size: int = 256, sources=None, out=None, stream=None,
+                      info=False):
+    """One of the paper's three GPU strategies (1 vertex-parallel, 2 edge-parallel, 3 host-
+    synchronised levels) as a baseline: same BC as bc_exact (sources None) or bc_sampled."""
+    out = _out(g, out)
+    srcs = _dev_u32(sources) if sources is not None else None
+    inf = bc_info() if info else None
+    _check(lib().bc_paper_strategy(g.handle, int(strategy), int(wg_size),
+                                   P(srcs.data_ptr()) if srcs is not None and srcs.numel() else None,
+                                   srcs.numel() if srcs is not None else -1, P(out.data_ptr()), _stream(stream),
+                                   ctypes.byref(inf) if inf is not None else None))
     return (out, inf.as_dict()) if info else out
 
 

@@ -2,6 +2,8 @@
 // single-graph entry points.  Batch, tuning and serving live in their own files.
 #include "bc_internal.h"
 
+#include <vector>
+
 #include <cstdio>
 
 namespace bcmi {
@@ -19,6 +21,7 @@ Graph::~Graph() {
     (void)hipSetDevice(device);
     (void)hipDeviceSynchronize();
     graph_scratch_free(*this);
+    strat_pool_delete(strat);
     if (row_ptr) (void)hipFree(row_ptr);
     if (col) (void)hipFree(col);
     if (csc_ptr) (void)hipFree(csc_ptr);
@@ -298,6 +301,36 @@ bc_status bc_batch(const bc_graph* gs, int32_t num_graphs, double* const* d_bcs,
         }
         const Knobs kn = resolve_knobs(*as_graph(gs[0]), t);
         run_batch(gs, num_graphs, d_bcs, kn, (hipStream_t)stream, infos, nullptr);
+    });
+}
+
+bc_status bc_paper_strategy(bc_graph gh, int32_t strategy, int32_t wg_size, const uint32_t* d_sources, int32_t k,
+                            double* d_bc, void* stream, bc_info* info) {
+    return guarded([&] {
+        Graph* g = as_graph(gh);
+        BC_REQUIRE(d_bc != nullptr, BC_E_INVAL, "null output array");
+        BC_REQUIRE(k <= 0 || d_sources != nullptr, BC_E_INVAL, "null source array");
+        std::lock_guard<std::mutex> lk(g->mu);
+        const hipStream_t st = (hipStream_t)stream;
+        const bool all = k < 0;
+        const uint32_t items = all ? (uint32_t)g->n : (uint32_t)k;
+        if (!all && k > 0) {   // the kernels trust their source ids
+            std::vector<uint32_t> h(k);
+            BC_HIP_TRY(hipMemcpyAsync(h.data(), d_sources, sizeof(uint32_t) * k, hipMemcpyDeviceToHost, st));
+            BC_HIP_TRY(hipStreamSynchronize(st));
+            for (uint32_t x : h) BC_REQUIRE(x < (uint32_t)g->n, BC_E_RANGE, "a source id is >= n");
+        }
+        StreamTimer tm(st, info != nullptr);
+        uint32_t levels = 0;
+        run_strategy(g->strat, *g, strategy, wg_size, all ? nullptr : d_sources, items, d_bc, st, &levels);
+        if (info) {
+            bc_info out{};
+            out.kernel_ms = tm.stop_ms();
+            out.n_sources = items;
+            out.levels_max = levels;
+            out.path = (uint32_t)(3 + strategy);
+            *info = out;
+        }
     });
 }
 

@@ -113,6 +113,7 @@ struct Graph {
     uint32_t zero_out_degree = 0;  // vertices with no out-edges (sources that reach nothing)
     // per-source scratch, grown on demand and reused between calls
     void* slots = nullptr;
+    struct StratPool* strat = nullptr;   // state of the paper's strategy baselines
     CallStats* stats = nullptr;    // device
     std::mutex mu;
     ~Graph();
@@ -237,6 +238,13 @@ size_t narrow_slot_bytes(uint32_t n);
 // the LDS tables are handed to `retry_launch` with caller ids
 void run_narrow_enqueue(NarrowPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc,
                         CallStats* stats, int slots_cap, hipStream_t st, RetryLaunch retry_launch, void* retry_ctx);
+
+// ---- the paper's three strategies as baselines (strategies.hip) ---------------------------
+void strat_pool_delete(StratPool* p);
+// strategy 1 vertex-parallel / 2 edge-parallel (one workgroup per source), 3 edge-parallel over
+// the grid with host-synchronised levels; sources in caller ids (null: all n); zeroes d_bc
+void run_strategy(StratPool*& pool, const Graph& g, int strategy, int wg, const uint32_t* d_sources, uint32_t k,
+                  double* d_bc, hipStream_t st, uint32_t* levels_max);
 
 // ---- tuning (tune.hip) -------------------------------------------------------------------
 Knobs resolve_knobs(Graph& g, const bc_tuning* t);
