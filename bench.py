@@ -13,7 +13,9 @@ HIP-event time), and the CPU oracle timed on a bounded sample of the same source
 
 Other workloads (--workload): rmat20 (scale 20, edge factor 16, 1,024 seeded sources),
 lattice (1024 x 1024 lattice with random edge orientation, 1,024 seeded sources), batch
-(4,096 R-MAT graphs of scale 6..12, edge factor 8, exact BC of each in one launch).
+(4,096 R-MAT graphs of scale 6..12, edge factor 8, exact BC of each in one launch), serve
+(Poisson request stream), paper (the paper's three strategies against the default path on
+BA digraphs).
 """
 from __future__ import annotations
 
@@ -223,6 +225,56 @@ def one_source_per_launch_ms(bcmi, torch, g, sources, reps):
     return (time.perf_counter() - t0) * 1e3 / min(reps, len(sources))
 
 
+def bench_paper(args, torch, bcmi, gg):
+    """The paper's comparison (section III) on its own workload, BA digraphs: exact BC time of
+    its three strategies (1 vertex-parallel, 2 edge-parallel, 3 host-synchronised levels) and of
+    the default path, over graph size at density 10, over density at 5,000 vertices, and over
+    workgroup size on 5,000 vertices / 49,950 edges."""
+
+    def exact_ms(g, strategy, wg=None):
+        out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        run = (lambda: bcmi.bc_exact(g, out=out)) if strategy == 0 else \
+            (lambda: bcmi.bc_paper_strategy(g, strategy, wg or 256, out=out))
+        run()
+        torch.cuda.synchronize()
+        reps = max(1, args.steps)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    def row(n, beta, seed):
+        g = bcmi.bc_build_csr(*gg.barabasi_albert(n, beta, seed))
+        ms = {name: exact_ms(g, s) for name, s in [("bcmi", 0), ("vertex", 1), ("edge", 2), ("host_sync", 3)]}
+        r = {"n": n, "m": g.m, "d": round(g.m / n, 2), "ms": {k: round(v, 3) for k, v in ms.items()},
+             "speedup_over_host_sync": {k: round(ms["host_sync"] / v, 2) for k, v in ms.items()}}
+        g.free()
+        print(f"paper: n={n} m={r['m']} {r['ms']}", file=sys.stderr, flush=True)
+        return r
+
+    size = [row(n, 5, 100 + n) for n in (1000, 2000, 5000, 10000)]
+    density = [row(5000, b, 200 + b) for b in (1, 2, 5, 10, 20, 30)]
+    g = bcmi.bc_build_csr(*gg.barabasi_albert(5000, 5, 0))
+    blocks = {name: {wg: round(exact_ms(g, strategy, wg), 3) for wg in (64, 128, 256, 512, 1024)}
+              for name, strategy in [("vertex", 1), ("edge", 2), ("host_sync", 3)]}
+    ref = {"n": g.n, "m": g.m, "bcmi_ms": exact_ms(g, 0)}
+    g.free()
+    value = ref["n"] * ref["m"] / (ref["bcmi_ms"] / 1e3) / 1e9
+    return {"metric": "GTEPS (sources x edges / s), exact BC on the paper's BA digraph workload", "value": value,
+            "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": ref["bcmi_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64+f64",
+            "data": "synthetic",
+            "config": {"workload": "paper-ba-n5000-m49950", "graph": "Barabasi-Albert digraph, n=5,000, "
+                       "beta=5 (m=49,950), seed 0", "sources": "all"},
+            "extra": {"graph_size_d10": size, "edge_density_n5000": density,
+                      "workgroup_size_ms": blocks,
+                      "strategies": {"vertex": "one workgroup per source, vertex-parallel levels",
+                                     "edge": "one workgroup per source, edge-parallel levels",
+                                     "host_sync": "whole grid per source, one launch per level, host-read flag",
+                                     "bcmi": "default path of bc_exact"}}}
+
+
 def bench_batch(args, torch, bcmi, gg):
     rng = np.random.default_rng(4096)
     scales = rng.integers(6, 13, size=4096)
@@ -345,7 +397,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat20", "lattice", "batch", "serve"])
+    ap.add_argument("--workload", default="rmat16",
+                    choices=["rmat16", "rmat20", "lattice", "batch", "serve", "paper"])
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="mean arrivals per second")
     ap.add_argument("--serve-max-scale", type=int, default=14)
@@ -384,6 +437,8 @@ def main():
         res = bench_batch(args, torch, bcmi, gg)
     elif args.workload == "serve":
         res = bench_serve(args, torch, bcmi, gg)
+    elif args.workload == "paper":
+        res = bench_paper(args, torch, bcmi, gg)
     else:
         res = bench_single(args, torch, bcmi, gg)
     print(json.dumps(res), flush=True)
