@@ -105,7 +105,7 @@ def test_serve_overlap_and_continuous_batching(bc):
     srv = bc.bc_serve_create(64 << 30)
     out_a = torch.empty(big.n, dtype=torch.float64, device="cuda")
     out_b = torch.empty(small.n, dtype=torch.float64, device="cuda")
-    SA = gg.uniform_sources(big.n, big.n, 1)
+    SA = np.tile(gg.uniform_sources(big.n, big.n, 1), 4)   # a multiset of 8 batched chunks
     ta = bc.bc_serve_submit(srv, big, SA, out_a)   # spans many ticks
     time.sleep(0.005)
     tb = bc.bc_serve_submit(srv, small, None, out_b)
