@@ -158,6 +158,27 @@ BC_API bc_status bc_batch(const bc_graph* gs, int32_t num_graphs, double* const*
  * sources; cached per device and graph class).  Synchronous. */
 BC_API bc_status bc_tune(bc_graph g, bc_tuning* out);
 
+/* Approximate BC from pivot sources (the sampling approximation cited in section I): k
+ * pivots drawn uniformly with replacement (SplitMix64 from `seed`), sampled BC scaled by n/k,
+ * an unbiased estimate of every BC(v).  k = ceil(ln(2n/delta) / (2 eps^2)), so that with
+ * probability >= 1 - delta every |estimate(v) - BC(v)| <= eps * n * (n - 2) (Hoeffding and a
+ * union bound over the n vertices); when k >= n the exact BC is computed instead (k = n).
+ * eps in (0, 1], delta in (0, 1).  d_bc: n doubles, overwritten.  k_out (nullable): k.
+ * h_pivots (nullable, host, capacity pivots_cap >= k): the pivots used (0..n-1 when exact).
+ * info (nullable) as for bc_sampled.  Errors: BC_E_INVAL, BC_E_NOMEM, BC_E_HIP.  Returns after
+ * the work is done. */
+BC_API bc_status bc_approx(bc_graph g, double eps, double delta, uint64_t seed, double* d_bc, int32_t* k_out,
+                           uint32_t* h_pivots, int32_t pivots_cap, void* stream, bc_info* info);
+
+/* Adaptive sampling for one vertex v: pivots (same generator) are taken in rounds of 64 until
+ * the sampled dependencies S = sum delta_s(v) reach c * n or max_samples pivots were used;
+ * the estimate n * S / k is written to *h_est (host), k to *k_out (nullable), the pivots to
+ * h_pivots (nullable, capacity pivots_cap >= max_samples).  Errors: BC_E_INVAL (c <= 0,
+ * max_samples <= 0, null estimate), BC_E_RANGE (v >= n), BC_E_NOMEM, BC_E_HIP. */
+BC_API bc_status bc_approx_vertex(bc_graph g, uint32_t v, double c, uint64_t seed, int32_t max_samples,
+                                  double* h_est, int32_t* k_out, uint32_t* h_pivots, int32_t pivots_cap,
+                                  void* stream);
+
 /* The three GPU strategies compared in the paper (section I, section III), rebuilt as baselines
  * for rerunning that comparison on its own workload (BA digraphs); not the fast path:
  *   strategy 1: one workgroup per source, vertex-parallel levels (every vertex tested each

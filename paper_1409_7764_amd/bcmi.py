@@ -75,14 +75,19 @@ def lib():
         L.bc_tune.argtypes = [P, ctypes.POINTER(bc_tuning)]
         L.bc_paper_strategy.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P, P,
                                         ctypes.POINTER(bc_info)]
+        L.bc_approx.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, P,
+                                ctypes.POINTER(ctypes.c_int32), P, ctypes.c_int32, P, ctypes.POINTER(bc_info)]
+        L.bc_approx_vertex.argtypes = [P, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P,
+                                       ctypes.c_int32, P]
         L.bc_serve_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(P)]
         L.bc_serve_submit.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_uint64)]
         L.bc_serve_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(bc_info)]
         L.bc_serve_destroy.argtypes = [P]
         for name in ["bc_build_csr", "bc_graph_info", "bc_graph_arrays", "bc_graph_order", "bc_graph_free", "bc_exact",
                      "bc_sampled",
-                     "bc_sssp", "bc_batch", "bc_tune", "bc_paper_strategy", "bc_serve_create", "bc_serve_submit",
-                     "bc_serve_poll", "bc_serve_destroy"]:
+                     "bc_sssp", "bc_batch", "bc_tune", "bc_paper_strategy", "bc_approx", "bc_approx_vertex",
+                     "bc_serve_create", "bc_serve_submit", "bc_serve_poll", "bc_serve_destroy"]:
             getattr(L, name).restype = ctypes.c_int32
         L.bc_last_error.restype = ctypes.c_char_p
         L.bc_version.restype = ctypes.c_char_p
@@ -232,6 +237,33 @@ def bc_paper_strategy(g: Graph, strategy: int, wg_size: int = 256, sources=None,
                                    srcs.numel() if srcs is not None else -1, P(out.data_ptr()), _stream(stream),
                                    ctypes.byref(inf) if inf is not None else None))
     return (out, inf.as_dict()) if info else out
+
+
+def bc_approx(g: Graph, eps: float, delta: float, seed: int, out=None, stream=None, info=False):
+    """Pivot-sampled BC scaled by n/k, k from a Hoeffding bound (exact BC when k >= n).
+    Returns (estimate, pivots as a numpy array[, info])."""
+    import numpy as np
+    out = _out(g, out)
+    cap = g.n
+    piv = np.zeros(max(cap, 1), dtype=np.uint32)
+    k = ctypes.c_int32(0)
+    inf = bc_info() if info else None
+    _check(lib().bc_approx(g.handle, float(eps), float(delta), int(seed), P(out.data_ptr()), ctypes.byref(k),
+                           piv.ctypes.data_as(P), cap, _stream(stream),
+                           ctypes.byref(inf) if inf is not None else None))
+    piv = piv[:k.value].copy()
+    return (out, piv, inf.as_dict()) if info else (out, piv)
+
+
+def bc_approx_vertex(g: Graph, v: int, c: float, seed: int, max_samples: int, stream=None):
+    """Adaptive sampling for one vertex: (estimate, pivots used)."""
+    import numpy as np
+    piv = np.zeros(max(int(max_samples), 1), dtype=np.uint32)
+    est = ctypes.c_double(0.0)
+    k = ctypes.c_int32(0)
+    _check(lib().bc_approx_vertex(g.handle, int(v), float(c), int(seed), int(max_samples), ctypes.byref(est),
+                                  ctypes.byref(k), piv.ctypes.data_as(P), int(max_samples), _stream(stream)))
+    return est.value, piv[:k.value].copy()
 
 
 _keep = []

@@ -2,6 +2,7 @@
 // single-graph entry points.  Batch, tuning and serving live in their own files.
 #include "bc_internal.h"
 
+#include <algorithm>
 #include <vector>
 
 #include <cstdio>
@@ -301,6 +302,109 @@ bc_status bc_batch(const bc_graph* gs, int32_t num_graphs, double* const* d_bcs,
         }
         const Knobs kn = resolve_knobs(*as_graph(gs[0]), t);
         run_batch(gs, num_graphs, d_bcs, kn, (hipStream_t)stream, infos, nullptr);
+    });
+}
+
+bc_status bc_approx(bc_graph gh, double eps, double delta, uint64_t seed, double* d_bc, int32_t* k_out,
+                    uint32_t* h_pivots, int32_t pivots_cap, void* stream, bc_info* info) {
+    return guarded([&] {
+        Graph* g = as_graph(gh);
+        BC_REQUIRE(d_bc != nullptr, BC_E_INVAL, "null output array");
+        const uint32_t n = (uint32_t)g->n;
+        const uint32_t k = hoeffding_pivots(n, eps, delta);
+        BC_REQUIRE(h_pivots == nullptr || pivots_cap >= (int32_t)k, BC_E_INVAL, "pivot buffer too small");
+        std::lock_guard<std::mutex> lk(g->mu);
+        const hipStream_t st = (hipStream_t)stream;
+        const Knobs kn = resolve_knobs(*g, nullptr);
+        RunArgs ra{};
+        ra.g = g;
+        ra.bc = d_bc;
+        std::vector<uint32_t> piv;
+        uint32_t* d_piv = nullptr;
+        if (k < n) {   // pivots, scaled by n/k
+            piv.resize(k);
+            draw_pivots(seed, n, k, piv.data());
+            BC_HIP_TRY(hipMalloc((void**)&d_piv, sizeof(uint32_t) * std::max<uint32_t>(k, 1)));
+            ra.sources = d_piv;
+            ra.num_items = k;
+        } else {       // the bound asks for n pivots or more: exact BC
+            ra.sources = nullptr;
+            ra.num_items = n;
+        }
+        try {
+            if (d_piv) BC_HIP_TRY(hipMemcpyAsync(d_piv, piv.data(), sizeof(uint32_t) * k, hipMemcpyHostToDevice, st));
+            StreamTimer tm(st, info != nullptr);
+            const int path = run_sources(ra, kn, st, *g);
+            if (k < n) scale_bc(d_bc, n, (double)n / (double)k, st);
+            if (info) {
+                const double ms = tm.stop_ms();
+                fill_info(*g, st, path, ms, ra.num_items, info);
+            }
+            BC_HIP_TRY(hipStreamSynchronize(st));
+        } catch (...) {
+            if (d_piv) {
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(d_piv);
+            }
+            throw;
+        }
+        if (d_piv) (void)hipFree(d_piv);
+        if (k_out) *k_out = (int32_t)k;
+        if (h_pivots) {
+            if (k < n) std::copy(piv.begin(), piv.end(), h_pivots);
+            else for (uint32_t i = 0; i < n; ++i) h_pivots[i] = i;
+        }
+    });
+}
+
+bc_status bc_approx_vertex(bc_graph gh, uint32_t v, double c, uint64_t seed, int32_t max_samples, double* h_est,
+                           int32_t* k_out, uint32_t* h_pivots, int32_t pivots_cap, void* stream) {
+    return guarded([&] {
+        Graph* g = as_graph(gh);
+        BC_REQUIRE(h_est != nullptr, BC_E_INVAL, "null estimate pointer");
+        BC_REQUIRE(c > 0.0, BC_E_INVAL, "c must be > 0");
+        BC_REQUIRE(max_samples > 0, BC_E_INVAL, "max_samples must be > 0");
+        const uint32_t n = (uint32_t)g->n;
+        BC_REQUIRE(v < n, BC_E_RANGE, "vertex id >= n");
+        BC_REQUIRE(h_pivots == nullptr || pivots_cap >= max_samples, BC_E_INVAL, "pivot buffer too small");
+        std::lock_guard<std::mutex> lk(g->mu);
+        const hipStream_t st = (hipStream_t)stream;
+        const Knobs kn = resolve_knobs(*g, nullptr);
+        constexpr uint32_t kRound = 64;   // pivots per round: one batch of the batched kernel
+        std::vector<uint32_t> piv((size_t)max_samples);
+        draw_pivots(seed, n, (uint32_t)max_samples, piv.data());
+        uint32_t* d_piv = nullptr;
+        double* d_part = nullptr;
+        double* d_tmp = nullptr;
+        double sum = 0.0;
+        uint32_t taken = 0;
+        try {
+            BC_HIP_TRY(hipMalloc((void**)&d_piv, sizeof(uint32_t) * piv.size()));
+            BC_HIP_TRY(hipMalloc((void**)&d_part, sizeof(double) * std::max<uint32_t>(n, 1)));
+            BC_HIP_TRY(hipMalloc((void**)&d_tmp, sizeof(double)));
+            BC_HIP_TRY(hipMemcpyAsync(d_piv, piv.data(), sizeof(uint32_t) * piv.size(), hipMemcpyHostToDevice, st));
+            while (taken < (uint32_t)max_samples && sum < c * (double)n) {
+                const uint32_t r = std::min<uint32_t>(kRound, (uint32_t)max_samples - taken);
+                RunArgs ra{};
+                ra.g = g;
+                ra.bc = d_part;
+                ra.sources = d_piv + taken;
+                ra.num_items = r;
+                run_sources(ra, kn, st, *g);
+                sum += read_bc_entry(d_part, v, d_tmp, st);   // the round's sum of delta_s(v)
+                taken += r;
+            }
+        } catch (...) {
+            (void)hipStreamSynchronize(st);
+            for (void* q : {(void*)d_piv, (void*)d_part, (void*)d_tmp})
+                if (q) (void)hipFree(q);
+            throw;
+        }
+        for (void* q : {(void*)d_piv, (void*)d_part, (void*)d_tmp})
+            if (q) (void)hipFree(q);
+        *h_est = taken ? (double)n * sum / (double)taken : 0.0;
+        if (k_out) *k_out = (int32_t)taken;
+        if (h_pivots) std::copy(piv.begin(), piv.begin() + taken, h_pivots);
     });
 }
 

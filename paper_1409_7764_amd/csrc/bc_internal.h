@@ -246,6 +246,12 @@ void strat_pool_delete(StratPool* p);
 void run_strategy(StratPool*& pool, const Graph& g, int strategy, int wg, const uint32_t* d_sources, uint32_t k,
                   double* d_bc, hipStream_t st, uint32_t* levels_max);
 
+// ---- approximate BC by source sampling (approx.hip) ------------------------------------------
+void draw_pivots(uint64_t seed, uint32_t n, uint32_t k, uint32_t* out);   // SplitMix64, uniform on [0, n)
+uint32_t hoeffding_pivots(uint32_t n, double eps, double delta);        // n when the bound needs >= n
+void scale_bc(double* d_bc, uint32_t n, double f, hipStream_t st);
+double read_bc_entry(const double* d_bc, uint32_t v, double* d_tmp, hipStream_t st);
+
 // ---- tuning (tune.hip) -------------------------------------------------------------------
 Knobs resolve_knobs(Graph& g, const bc_tuning* t);
 Knobs default_knobs(const Graph& g);
