@@ -1,8 +1,9 @@
 """Summarise rocprofv3 output of a bench.py run into a short text record.
 
 Inputs: the directory of a `rocprofv3 --kernel-trace --stats --output-format csv` run, and
-the directories of two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
-`bench.py --calibrate-copy` (one plain 2 GiB device-to-device copy precedes the steps).
+optionally the directories of two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
+`bench.py --calibrate-copy` (one plain 2 GiB device-to-device copy precedes the steps); without
+them the record holds the kernel trace alone.
 The counters are scaled by what they read for that copy (its true traffic is known), and
 the per-launch HBM bytes of the named kernel are written to profiles/traffic.json under the
 workload name, together with the hash of the kernel sources they were taken on.
@@ -44,8 +45,8 @@ def main(argv=None):
     ap.add_argument("--workload", required=True)
     ap.add_argument("--kernel", required=True, help="substring of the dominant kernel's name")
     ap.add_argument("--kt", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
     ap.add_argument("--cmd", required=True, help="the commands that produced the inputs")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
@@ -63,6 +64,13 @@ def main(argv=None):
         lines.append(f"| `{name[:90]}` | {r['Calls']} | {tot:.3f} | {avg:.3f} | {float(r['Percentage']):.1f} |")
         if a.kernel in name and avg_ms is None:
             avg_ms = avg
+
+    if not (a.fetch and a.write):
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+        with open(a.out, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return
 
     def factor(rows, truth_bytes):
         copies = [v for k, g, v in rows if "copyBuffer" in k and v > 1024]
