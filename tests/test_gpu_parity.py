@@ -548,6 +548,52 @@ def test_lattice_1024_sampled_subset(bc):
 # ---------------------------------------------------------------------------------------
 # a8-a9: batch of uneven graphs, one captured launch per class, replayed
 # ---------------------------------------------------------------------------------------
+def test_stream_ordered_calls(bc):
+    """The calls are stream-ordered: on a side stream, with no host synchronisation, a torch op
+    queued behind the call on the same stream sees the finished result; two graphs on two
+    streams run concurrently; a sampled call reads a source list produced on its stream."""
+    import torch
+    n, u, v = gg.rmat(11, 16, 4)
+    want = oracle_exact("rmat11", n, u, v)[0]
+    g = bc.bc_build_csr(n, u, v)
+    n2, u2, v2 = gg.barabasi_albert(1500, 4, 5)
+    want2 = oracle.bc(oracle.Graph(n2, u2, v2))[0]
+    g2 = bc.bc_build_csr(n2, u2, v2)
+    S = gg.uniform_sources(n, 150, 6)
+    want_s = oracle.bc(oracle.Graph(n, u, v), S)[0]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for path in PATHS:
+        say("streams", path)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s1):
+            out1 = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+            bc.bc_exact(g, out=out1, tuning=force(bc, path), stream=s1)
+            twice1 = out1 * 2.0
+            src = torch.from_numpy(S.view(np.int32)).cuda().flip(0).flip(0)   # made on s1
+            out3 = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+            bc.bc_sampled(g, src, out=out3, tuning=force(bc, path), stream=s1)
+            twice3 = out3 * 2.0
+        with torch.cuda.stream(s2):
+            out2 = torch.full((n2,), -1.0, dtype=torch.float64, device="cuda")
+            bc.bc_exact(g2, out=out2, tuning=force(bc, path), stream=s2)
+            twice2 = out2 * 2.0
+        s1.synchronize()
+        s2.synchronize()
+        rel_close(np_of(twice1) / 2.0, want, what=f"{path} stream 1")
+        rel_close(np_of(twice3) / 2.0, want_s, what=f"{path} stream 1 sampled")
+        rel_close(np_of(twice2) / 2.0, want2, what=f"{path} stream 2")
+    say("streams batch")
+    with torch.cuda.stream(s1):
+        outs = [torch.full((x.n,), -1.0, dtype=torch.float64, device="cuda") for x in (g, g2)]
+        bc.bc_batch([g, g2], outs, stream=s1)
+        twice = [o * 2.0 for o in outs]
+    s1.synchronize()
+    rel_close(np_of(twice[0]) / 2.0, want, what="batch stream g")
+    rel_close(np_of(twice[1]) / 2.0, want2, what="batch stream g2")
+    g.free()
+    g2.free()
+
+
 def test_batch_matches_oracle_and_replays(bc):
     import torch
     rng = np.random.default_rng(77)
