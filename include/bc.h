@@ -21,8 +21,10 @@
  *     The library owns the graph's CSR/CSC arrays and all scratch memory until the handle
  *     is freed.
  *   - `stream` is a hipStream_t (NULL = the null stream).  bc_build_csr, bc_exact,
- *     bc_sampled and bc_batch are stream-ordered.  Passing a non-NULL `info` makes the call
- *     wait for its own work on that stream and fills `info` before returning.
+ *     bc_sampled and bc_batch are stream-ordered: their device work follows what the caller
+ *     queued on `stream` before the call, and work queued after it sees their results.
+ *     bc_build_csr also waits for its build before returning.  Passing a non-NULL `info`
+ *     makes a call wait for its own work on that stream and fill `info` before returning.
  *   - Calls that share a graph handle must be ordered with respect to each other (one
  *     stream, or synchronised): the handle's per-source scratch is reused between calls.
  *   - Return value: BC_OK (0) or a negative error code; bc_last_error() gives a message.
