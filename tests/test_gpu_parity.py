@@ -494,21 +494,28 @@ def test_rmat_scale16_sampled_subset(bc):
 
 
 def test_rmat_scale16_exact_properties(bc):
-    """Full exact run in the benchmark's configuration: equals the sum of sampled runs over a
-    partition of the vertex set, has exact zeros where no path can pass (no in- or no
-    out-edges), and a seeded subset matches the oracle."""
+    """Full exact run in the benchmark's configuration (automatic path and knobs): every
+    vertex's BC and the exact work counters equal the oracle's over all 65,536 sources; the
+    result equals the sum of sampled runs over a partition of the vertex set, and has exact
+    zeros where no path can pass (no in- or no out-edges)."""
     n, u, v = gg.rmat(16, 16, 16)
     g = bc.bc_build_csr(n, u, v)
     say("rmat16 exact")
     full, info = bc.bc_exact(g, info=True)
     full = np_of(full)
-    assert info["n_sources"] == n
+    assert info["n_sources"] == n and info["path"] == PATH_CODE["batched"]
+    o = oracle.Graph(n, u, v)
+    say("rmat16 exact: oracle over every source")
+    want, ovf, st = oracle.bc(o)
+    assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    assert info["levels_max"] == int(st[:, 3].max())
+    rel_close(full, want, what="rmat16 exact")
     perm = np.random.default_rng(5).permutation(n).astype(np.uint32)
     acc = np.zeros(n)
     for part in np.array_split(perm, 3):
         acc += np_of(bc.bc_sampled(g, part))
     rel_close(full, acc, 1e-11)
-    o = oracle.Graph(n, u, v)
     indeg = np.bincount(o.col, minlength=n)
     outdeg = np.diff(o.row_ptr.astype(np.int64))
     assert np.all(full[(indeg == 0) | (outdeg == 0)] == 0)
