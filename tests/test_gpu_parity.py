@@ -525,15 +525,23 @@ def test_rmat_scale16_exact_properties(bc):
 
 @pytest.mark.slow
 def test_rmat_scale20_sampled_subset(bc):
+    """The benchmark's R-MAT scale-20 workload (its 1,024 sources, automatic path): every
+    vertex's BC and the work counters equal the oracle's over the same sources, and the run
+    equals the sum of runs over a split of the source list."""
     n, u, v = gg.rmat(20, 16, 20)
     g = bc.bc_build_csr(n, u, v)
     S = gg.uniform_sources(n, 1024, 2020)
     say("rmat20 sampled 1024")
-    allk = np_of(bc.bc_sampled(g, S))
-    sub = S[:24]
-    got = np_of(bc.bc_sampled(g, sub))
-    want, _, _ = oracle.bc(oracle.Graph(n, u, v), sub)
-    rel_close(got, want)
+    allk, info = bc.bc_sampled(g, S, info=True)
+    allk = np_of(allk)
+    assert info["n_sources"] == len(S) and info["path"] == PATH_CODE["batched"]
+    say("rmat20 sampled 1024: oracle")
+    want, ovf, st = oracle.bc(oracle.Graph(n, u, v), S)
+    assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    assert info["levels_max"] == int(st[:, 3].max())
+    rel_close(allk, want, what="rmat20 sampled 1024")
+    got = np_of(bc.bc_sampled(g, S[:24]))
     rest = np_of(bc.bc_sampled(g, S[24:]))
     rel_close(allk, got + rest, 1e-11)
     g.free()
@@ -541,14 +549,20 @@ def test_rmat_scale20_sampled_subset(bc):
 
 @pytest.mark.slow
 def test_lattice_1024_sampled_subset(bc):
+    """The benchmark's lattice workload (1024 x 1024, its 1,024 sources, automatic path for a
+    deep graph): every vertex's BC and the work counters equal the oracle's."""
     n, u, v = gg.grid_random_orientation(1024, 1024, 1)
     g = bc.bc_build_csr(n, u, v)
-    S = gg.uniform_sources(n, 48, 1024)
-    say("lattice1024 sampled 48")
+    S = gg.uniform_sources(n, 1024, 1024)
+    say("lattice1024 sampled 1024")
     got, info = bc.bc_sampled(g, S, info=True)
-    want, ovf, _ = oracle.bc(oracle.Graph(n, u, v), S)
+    assert info["n_sources"] == len(S)
+    say("lattice1024 sampled 1024: oracle")
+    want, ovf, st = oracle.bc(oracle.Graph(n, u, v), S)
     assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
-    rel_close(np_of(got), want)
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    assert info["levels_max"] == int(st[:, 3].max())
+    rel_close(np_of(got), want, what="lattice1024 sampled 1024")
     g.free()
 
 
