@@ -615,6 +615,28 @@ def test_stream_ordered_calls(bc):
     g2.free()
 
 
+@pytest.mark.slow
+def test_batch_bench_workload(bc):
+    """The benchmark's batch, 4,096 R-MAT graphs of scales 6 to 12 (edge factor 8) in one
+    call with the default knobs: every graph's BC equals the oracle's exact BC."""
+    import torch
+    rng = np.random.default_rng(4096)
+    scales = rng.integers(6, 13, size=4096)
+    specs = [gg.rmat(int(sc), 8, 4096_000 + i) for i, sc in enumerate(scales)]
+    graphs = [bc.bc_build_csr(n, u, v) for n, u, v in specs]
+    say("batch of 4096 graphs")
+    outs, infos = bc.bc_batch(graphs, info=True)
+    torch.cuda.synchronize()
+    say("batch of 4096 graphs: oracle")
+    for i, (n, u, v) in enumerate(specs):
+        want, ovf, st = oracle.bc(oracle.Graph(n, u, v))
+        assert infos[i]["n_sources"] == n and infos[i]["path"] == PATH_CODE["lds"]
+        assert infos[i]["n_sigma_fp64_fallback"] == int(ovf.sum())
+        rel_close(np_of(outs[i]), want, what=f"graph {i} (scale {scales[i]})")
+    for g in graphs:
+        g.free()
+
+
 def test_batch_matches_oracle_and_replays(bc):
     import torch
     rng = np.random.default_rng(77)
