@@ -195,3 +195,54 @@ def test_autotune_keeps_results(bc):
     rel_close(bc.bc_exact(g2).cpu().numpy(), want)
     g.free()
     g2.free()
+
+
+@pytest.mark.slow
+def test_serve_bench_workload(bc):
+    """The benchmark's served stream, replayed: 256 requests over a pool of 64 resident
+    R-MAT graphs (scales 8 to 14, edge factors 4 to 16), 70 % exact and 30 % on 256 sampled
+    sources, submitted at the same Poisson arrival times (2,000 per second).  Every request's
+    result equals the oracle's."""
+    import torch
+    rng = np.random.default_rng(5)
+    pool, coo = [], []
+    for i in range(64):
+        sc = int(rng.integers(8, 15))
+        ef = int(rng.integers(4, 17))
+        n, u, v = gg.rmat(sc, ef, 5000 + i)
+        coo.append((n, u, v))
+        pool.append(bc.bc_build_csr(n, u, v))
+    arrive = np.cumsum(rng.exponential(1.0 / 2000.0, size=256))
+    reqs = []
+    for i in range(256):
+        gi = int(rng.integers(0, len(pool)))
+        if rng.random() < 0.7:
+            reqs.append((gi, None))
+        else:
+            reqs.append((gi, gg.uniform_sources(pool[gi].n, min(256, pool[gi].n), 77 + i)))
+    outs = [torch.full((pool[gi].n,), -1.0, dtype=torch.float64, device="cuda") for gi, _ in reqs]
+    torch.cuda.synchronize()
+    srv = bc.bc_serve_create(200 << 30)
+    tickets = []
+    t0 = time.perf_counter()
+    for (gi, S), out, at in zip(reqs, outs, arrive):
+        while time.perf_counter() - t0 < at:
+            pass
+        tickets.append(bc.bc_serve_submit(srv, pool[gi], S, out))
+    print("served stream: submitted", flush=True)
+    infos = [wait(bc, srv, t, timeout=300.0) for t in tickets]
+    bc.bc_serve_destroy(srv)
+    print("served stream: done; oracle", flush=True)
+    exact = {}
+    for i, ((gi, S), out, inf) in enumerate(zip(reqs, outs, infos)):
+        n, u, v = coo[gi]
+        if S is None:
+            if gi not in exact:
+                exact[gi] = oracle.bc(oracle.Graph(n, u, v))[0]
+            want = exact[gi]
+        else:
+            want = oracle.bc(oracle.Graph(n, u, v), S)[0]
+        assert inf["n_sources"] == (n if S is None else len(S))
+        rel_close(out.cpu().numpy(), want, what=f"request {i} (graph {gi}, {'exact' if S is None else 'sampled'})")
+    for g in pool:
+        g.free()
