@@ -39,7 +39,6 @@
 #include "bc_internal.h"
 
 #include <algorithm>
-#include <cstdlib>
 
 namespace bcmi {
 
@@ -987,12 +986,11 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     uint32_t* plan_count = p.small + 80;
     uint32_t* retry_count = p.small + 81;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, st, p.small, 128u);
-    // the batched kernel runs on the caller's numbering unless BCMI_MSB_RELABEL=1
-    const char* mr = std::getenv("BCMI_MSB_RELABEL");
-    const bool rel = mr && mr[0] == '1' && g.perm;
-    const uint32_t* krow = rel ? g.prow : g.row_ptr;
-    const uint32_t* kcol = rel ? g.pcol : g.col;
-    const uint32_t* kperm = rel ? g.perm : nullptr;
+    // the batched kernel runs on the caller's numbering: sources batched by the batching order
+    // share more of their rows there than on the copy relabelled by in-degree
+    const uint32_t* krow = g.row_ptr;
+    const uint32_t* kcol = g.col;
+    const uint32_t* kperm = nullptr;
     if (!sources && g.order) {
         const uint32_t active = (uint32_t)(g.n - g.zero_out_degree);
         const unsigned gp = std::max(1u, std::min<unsigned>((active + 255) / 256, 2048));
@@ -1016,7 +1014,7 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.row_ptr = krow;
     a.col = kcol;
     a.bc = bc;
-    a.iperm = rel ? g.iperm : nullptr;
+    a.iperm = nullptr;
     a.plan = p.plan;
     a.plan_count = plan_count;
     a.retry = p.retry;
@@ -1050,7 +1048,7 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
         e = hipLaunchCooperativeKernel(msb_fn(wg), dim3(std::max(1, grid / 2)), dim3(wg), args, 0, st);
     }
     BC_HIP_TRY(e);
-    retry_launch(retry_ctx, p.retry, retry_count, std::max<uint32_t>(k, n), rel, st);
+    retry_launch(retry_ctx, p.retry, retry_count, std::max<uint32_t>(k, n), false, st);
 }
 
 }  // namespace bcmi
