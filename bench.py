@@ -426,9 +426,9 @@ def main():
                     help="run one plain 2 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the method shards over sources with one final sum of the "
-              "per-GPU BC arrays, and this build runs and reports the single-GPU share only "
-              "(--gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU (--gpus 1): the method would shard over sources with one "
+              "final sum of the per-GPU BC arrays, and only the single-GPU share is run and reported.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1409_7764_amd import bcmi, graphgen as gg

@@ -52,3 +52,15 @@ def test_null_handle_errors_without_device(libpath):
     assert lib.bc_graph_info(None, None, None) == -1          # BC_E_INVAL
     lib.bc_last_error.restype = ctypes.c_char_p
     assert b"null graph" in lib.bc_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU: asking for more exits with a message, before any
+    device work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
