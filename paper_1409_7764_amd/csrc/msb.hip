@@ -6,9 +6,10 @@
 // level for all of those sources.  Per-(vertex, source) state lives in 64-wide rows, so the
 // per-source updates of one edge are one coalesced row access instead of 64 scattered ones:
 //   seen[v]     sources that reached v at a level <= d         (64-bit mask)
-//   nxt[v]      sources reaching v at level d+1 (forward); the level-(d+1) masks, scattered,
-//               during the backward sweep
+//   nxt[v]      sources reaching v at level d+1 (forward)
 //               (seen and nxt of a vertex share one 16-byte record: one gather per edge)
+//   bnx[v]      backward sweep: the level-(d+1) masks, scattered into a dense 8-byte array
+//               (twice as many vertices per cache line as the records; seen is not needed)
 //   sig[v][s]   shortest-path count sigma_s(v) (uint32: a 256-byte row)
 //   psi[v][s]   psi_s(v) = (1 + delta_s(v)) / sigma_s(v) (double), written when the backward
 //               sweep finishes v's level
@@ -84,6 +85,8 @@ struct MsbArgs {
     uint32_t team_size;          // workgroups per team; 0 = as many as the batch count allows
     uint32_t pool_teams;         // team slots in the pool
     uint32_t sig_cap;            // largest count c with c * (largest in-degree) < 2^32
+    uint64_t* bnx;               // [teams][n]: backward sweep, level-(d+1) masks; zero between batches
+    uint64_t bnx_stride;
 };
 
 namespace {
@@ -428,6 +431,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     const Masks mk{a.masks + (size_t)team * a.mask_stride};
     uint32_t* sig = a.sig + (size_t)team * a.sig_stride;
     double* psi = a.psi + (size_t)team * a.psi_stride;
+    uint64_t* bnx = a.bnx + (size_t)team * a.bnx_stride;
     double* hacc = a.hacc + (size_t)blockIdx.x * a.hub_rows * 64;
     double* bcp = a.bcp + (size_t)team * a.cap;
     constexpr uint32_t HL = WG / 8;   // accumulator rows in LDS
@@ -573,7 +577,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 const uint32_t lo_d = lvl[dd], hi_d = lvl[dd + 1];
                 const uint32_t lo_n = lvl[dd + 1], hi_n = lvl[dd + 2];
                 if (leader && tid == 0) ctl->cc = 0;
-                for (uint32_t i = lo_n + gtid; i < hi_n; i += gthreads) mk.nxt(lv[i]) = lm[i] & ~ovf;
+                for (uint32_t i = lo_n + gtid; i < hi_n; i += gthreads) bnx[lv[i]] = lm[i] & ~ovf;
                 if (!team_sync(L, ctl, W, a.stats)) {
                     aborted = true;
                     break;
@@ -631,7 +635,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                         uint64_t sm = 0;
                         if (e < e1) {
                             w = a.col[e];
-                            sm = fj & mk.nxt(w);
+                            sm = fj & bnx[w];
                         }
                         dagc += (uint32_t)__builtin_popcountll(sm);
                         // lane per source: sum psi over the unit's successors, taken from the
@@ -679,7 +683,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                     if (tid == 0) L.nhub = 0;
                     __syncthreads();
                 }
-                // no clearing pass: a stale mask left in nxt[w] by a deeper level L >= d + 2
+                // no clearing pass: a stale mask left in bnx[w] by a deeper level L >= d + 2
                 // never meets an entry of level d with an edge to w (such a source would
                 // reach w within d + 1), and the reset clears every listed vertex's masks
             }
@@ -697,6 +701,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             const uint32_t v = lv[i];
             const uint64_t m = lm[i];
             mk.clear(v);
+            bnx[v] = 0ull;
             if (!stopped && (m & ~ovf)) {
                 const double c = bcp[i];
                 if (c != 0.0) unsafeAtomicAdd(&a.bc[a.iperm ? a.iperm[v] : v], c);
@@ -870,9 +875,9 @@ constexpr uint64_t kStaggerWords = 37 * 512;
 struct MsbPool {
     int teams = 0, wgs = 0;
     uint32_t n = 0, cap = 0, max_levels = 0, hub_rows = 0;
-    uint64_t mask_stride = 0, sig_stride = 0, psi_stride = 0;
+    uint64_t mask_stride = 0, sig_stride = 0, psi_stride = 0, bnx_stride = 0;
     TeamCtl* ctl = nullptr;
-    uint64_t *masks = nullptr, *lst_m = nullptr;
+    uint64_t *masks = nullptr, *lst_m = nullptr, *bnx = nullptr;
     uint32_t* sig = nullptr;
     double *psi = nullptr, *bcp = nullptr;
     double* hacc = nullptr;
@@ -885,12 +890,12 @@ struct MsbPool {
 };
 
 size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels) {
-    return sizeof(TeamCtl) + (size_t)n * (16 + 256 + 512) + 4 * kStaggerWords * 8 + (size_t)cap * 20 +
+    return sizeof(TeamCtl) + (size_t)n * (16 + 8 + 256 + 512) + 4 * kStaggerWords * 8 + (size_t)cap * 20 +
            4 * ((size_t)max_levels + 2);
 }
 
 void msb_pool_free(MsbPool& p) {
-    for (void* q : {(void*)p.ctl, (void*)p.masks, (void*)p.sig, (void*)p.psi, (void*)p.bcp, (void*)p.lst_m, (void*)p.hacc,
+    for (void* q : {(void*)p.ctl, (void*)p.masks, (void*)p.bnx, (void*)p.sig, (void*)p.psi, (void*)p.bcp, (void*)p.lst_m, (void*)p.hacc,
                     (void*)p.lst_v, (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small, (void*)p.bhist})
         if (q) (void)hipFree(q);
     p = MsbPool{};
@@ -927,8 +932,10 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     p.mask_stride = 2 * (uint64_t)n + kStaggerWords / 4;   // even: records stay 16-byte aligned
     p.sig_stride = (uint64_t)n * 64 + 2 * kStaggerWords;
     p.psi_stride = (uint64_t)n * 64 + kStaggerWords;
+    p.bnx_stride = (uint64_t)n + kStaggerWords / 8;
     BC_HIP_TRY(hipMalloc((void**)&p.ctl, (size_t)teams * sizeof(TeamCtl)));
     BC_HIP_TRY(hipMalloc((void**)&p.masks, (size_t)teams * p.mask_stride * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.bnx, (size_t)teams * p.bnx_stride * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.sig, (size_t)teams * p.sig_stride * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.psi, (size_t)teams * p.psi_stride * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.hacc, (size_t)wgs * hub_rows * 512));
@@ -943,6 +950,9 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     const size_t words = (size_t)teams * p.mask_stride;
     const unsigned g1 = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.masks, words);
+    const size_t bwords = (size_t)teams * p.bnx_stride;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<size_t>((bwords + 255) / 256, 65536)), dim3(256), 0, st,
+                       p.bnx, bwords);
     const size_t swords = (size_t)teams * p.sig_stride / 2;   // counts, as 64-bit words
     const unsigned g2 = (unsigned)std::min<size_t>((swords + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u64, dim3(g2), dim3(256), 0, st, (uint64_t*)p.sig, swords);
@@ -1039,6 +1049,8 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.team_size = team_knob > 0 ? (uint32_t)team_knob : 0u;
     a.pool_teams = (uint32_t)std::min<long>(p.teams, teams);   // a reused pool may hold more
     a.sig_cap = g.max_in_degree ? (uint32_t)(0xffffffffull / g.max_in_degree) : 0xffffffffu;
+    a.bnx = p.bnx;
+    a.bnx_stride = p.bnx_stride;
     void* args[] = {&a};
     // members of a team wait for each other at level boundaries: a cooperative launch
     // guarantees that every workgroup of the grid is resident at once
