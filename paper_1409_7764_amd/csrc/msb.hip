@@ -252,7 +252,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total,
 // Collects a level: every vertex whose next-mask is non-zero becomes an entry (w, mask) of
 // the team's level list; the mask is folded into seen and the next-mask cleared.  Each
 // thread takes kScanUnroll vertices per pass (loads first), each wavefront one list append.
-constexpr int kScanUnroll = 4;
+constexpr int kScanUnroll = 8;
 __device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, const Masks mk, uint32_t* lv, uint64_t* lm, uint32_t first, uint32_t stride,
                                                   uint32_t n) {
     const unsigned lane = lane_id();
