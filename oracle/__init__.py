@@ -32,19 +32,27 @@ class _Stats(ctypes.Structure):
 def _load():
     global _lib
     if _lib is None:
-        path = _build.build(force=False)
-        lib = ctypes.CDLL(path)
-        P = ctypes.c_void_p
-        lib.oracle_simple_adjacency.restype = ctypes.c_int64
-        lib.oracle_simple_adjacency.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P]
-        lib.oracle_brandes_source.restype = ctypes.c_int
-        lib.oracle_brandes_source.argtypes = [ctypes.c_int32, P, P, ctypes.c_uint32, P, P, P, P, P, P,
-                                              ctypes.POINTER(_Stats)]
-        lib.oracle_bc.restype = ctypes.c_int
-        lib.oracle_bc.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int64, P, P, P, ctypes.c_int]
-        lib.oracle_max_threads.restype = ctypes.c_int
-        _lib = lib
+        use_native(False)
     return _lib
+
+
+def use_native(native: bool) -> str:
+    """Load the generic build, or the host-tuned one (-O3 -march=native, compiled here and now);
+    returns the path of the library loaded."""
+    global _lib
+    path = _build.build_native() if native else _build.build(force=False)
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.oracle_simple_adjacency.restype = ctypes.c_int64
+    lib.oracle_simple_adjacency.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P]
+    lib.oracle_brandes_source.restype = ctypes.c_int
+    lib.oracle_brandes_source.argtypes = [ctypes.c_int32, P, P, ctypes.c_uint32, P, P, P, P, P, P,
+                                          ctypes.POINTER(_Stats)]
+    lib.oracle_bc.restype = ctypes.c_int
+    lib.oracle_bc.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int64, P, P, P, ctypes.c_int]
+    lib.oracle_max_threads.restype = ctypes.c_int
+    _lib = lib
+    return path
 
 
 def _ptr(a):

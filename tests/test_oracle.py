@@ -280,3 +280,74 @@ def test_linearity_and_multiset(orc):
     e1, _, _ = orc.bc(g, threads=1)
     e2, _, _ = orc.bc(g, np.arange(n, dtype=np.uint32), threads=3)
     rel_close(e1, e2, 1e-12)
+
+
+# --------------------------------------------------------------------------------------
+# per-source work counters (section I's method visits every vertex reached from s and
+# examines each of their out-edges once; the shortest-path DAG edges are the (v, w) with
+# d(s, w) = d(s, v) + 1; the levels are the distinct finite distances): each counter
+# against its definition on scipy's BFS distances, and against closed forms
+# --------------------------------------------------------------------------------------
+def counters_from_distances(n, row_ptr, col, d_row):
+    """(reached, examined, dag_edges, levels) of one source from its distance row."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    fin = np.isfinite(d_row)
+    outdeg = np.diff(row_ptr)
+    src = np.repeat(np.arange(n), outdeg)
+    tail_ok = fin[src]
+    dag = int(np.sum(tail_ok & fin[col] & (d_row[col] == d_row[src] + 1)))
+    return (int(fin.sum()), int(outdeg[fin].sum()), dag, int(d_row[fin].max()) + 1)
+
+
+def _counter_graphs():
+    return {
+        "rmat7": gg.rmat(7, 8, 1),
+        "rmat9": gg.rmat(9, 4, 2),
+        "grid_dag": gg.grid_dag(6, 9),
+        "lattice": gg.grid_random_orientation(12, 10, 3),
+        "diamonds70": gg.diamond_chain(70),
+    }
+
+
+@pytest.mark.parametrize("name", sorted(_counter_graphs()))
+def test_counters_vs_scipy_distances(orc, name):
+    n, u, v = _counter_graphs()[name]
+    g = orc.Graph(n, u, v)
+    d = _scipy_dist(n, g.row_ptr, g.col)
+    S = np.arange(n, dtype=np.uint32) if n <= 600 else gg.uniform_sources(n, 300, 5)
+    _, ovf, stats = orc.bc(g, S, threads=3)
+    for i, s in enumerate(S.tolist()):
+        want = counters_from_distances(n, g.row_ptr, g.col, d[s])
+        assert tuple(int(x) for x in stats[i]) == want, (name, s)
+    for s in S[:: max(1, len(S) // 12)].tolist():
+        r = orc.brandes_source(g, s)
+        want = counters_from_distances(n, g.row_ptr, g.col, d[s])
+        assert (r["reached"], r["examined"], r["dag_edges"], r["levels"]) == want, (name, s)
+    if name == "diamonds70":   # the first sources recount in double precision, once
+        assert ovf[0] == 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 9, 31])
+def test_counters_closed_form_path(orc, n):
+    # from vertex s of a directed path: n - s reached, n - 1 - s edges examined, all of them
+    # on shortest paths, n - s levels
+    g = orc.Graph(*gg.directed_path(n))
+    _, _, stats = orc.bc(g)
+    for s in range(n):
+        assert stats[s].tolist() == [n - s, n - 1 - s, n - 1 - s, n - s]
+
+
+@pytest.mark.parametrize("rows,cols", [(4, 7), (34, 34), (35, 35)])
+def test_counters_closed_form_grid_dag(orc, rows, cols):
+    # from the corner of a monotone grid DAG every vertex is reached, every edge is
+    # examined and lies on a shortest path, and the levels are the rows + cols - 1
+    # anti-diagonals; on 35 x 35 the corner's counts overflow 64 bits and the search is
+    # repeated in double precision, which must not count anything twice
+    g = orc.Graph(*gg.grid_dag(rows, cols))
+    edges = rows * (cols - 1) + cols * (rows - 1)
+    r = orc.brandes_source(g, 0)
+    assert r["overflow"] == (rows + cols - 2 >= 68)
+    assert (r["reached"], r["examined"], r["dag_edges"], r["levels"]) == (rows * cols, edges, edges, rows + cols - 1)
+    _, ovf, stats = orc.bc(g, np.array([0], np.uint32))
+    assert stats[0].tolist() == [rows * cols, edges, edges, rows + cols - 1]

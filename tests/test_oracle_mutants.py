@@ -31,6 +31,17 @@ MUTANTS = {
     "double_count_adds_one": ("sigma_f[w] += sigma_f[v];", "sigma_f[w] += 1.0;"),
     "forward_order_accumulation": ("for (int64_t i = count - 1; i >= 0; --i) {",
                                    "for (int64_t i = 0; i < count; ++i) {"),
+    # slips in the per-source work counters
+    "levels_off_by_one": ("st->levels = (int64_t)deepest + 1;", "st->levels = (int64_t)deepest;"),
+    "reached_excludes_source": ("st->reached = tail;", "st->reached = tail - 1;"),
+    "dag_counted_before_test": ("            if (dist[w] == dist[v] + 1) {         /* (v,w) lies on a shortest path */\n"
+                                "                ++dag;",
+                                "            ++dag;\n"
+                                "            if (dist[w] == dist[v] + 1) {"),
+    "dag_counted_on_first_visit": ("                order[tail++] = w;\n", "                order[tail++] = w;\n                ++dag;\n"),
+    "examined_per_vertex": [("            ++examined;\n", ""),
+                            ("        uint32_t v = order[head++];\n", "        uint32_t v = order[head++];\n        ++examined;\n")],
+    "recount_adds_counters": ("st->examined = examined;", "st->examined += examined;"),
 }
 
 
@@ -41,9 +52,9 @@ def _load_copy(tmp, name, mutation):
     src = os.path.join(dst, "brandes.c")
     text = open(src).read()
     if mutation is not None:
-        old, new = mutation
-        assert text.count(old) == 1, f"mutation anchor not unique: {old!r}"
-        text = text.replace(old, new)
+        for old, new in (mutation if isinstance(mutation, list) else [mutation]):
+            assert text.count(old) == 1, f"mutation anchor not unique: {old!r}"
+            text = text.replace(old, new)
         open(src, "w").write(text)
     spec = importlib.util.spec_from_file_location(name, os.path.join(dst, "__init__.py"),
                                                   submodule_search_locations=[dst])
@@ -91,6 +102,25 @@ def _pin_failures(orc):
     r = orc.brandes_source(g, 0)
     want = [float(math.comb(i + j, i)) for i in range(35) for j in range(35)]
     check("grid_sigma_f", close(r["sigma_f"], want, 1e-13))
+    # work counters: closed form on the overflowing grid DAG (every vertex reached, every
+    # edge examined and on a shortest path, 69 levels), and the definitions on scipy's BFS
+    # distances for every source of a small R-MAT graph
+    check("grid_counters", (r["reached"], r["examined"], r["dag_edges"], r["levels"]) == (1225, 2380, 2380, 69))
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    n, u, v = gg.rmat(7, 8, 1)
+    g = orc.Graph(n, u, v)
+    a = csr_matrix((np.ones(g.m), g.col.astype(np.int64), g.row_ptr.astype(np.int64)), shape=(n, n))
+    d = shortest_path(a, method="D", directed=True, unweighted=True)
+    _, _, stats = orc.bc(g, threads=2)
+    outdeg = np.diff(g.row_ptr.astype(np.int64))
+    src = np.repeat(np.arange(n), outdeg)
+    col = g.col.astype(np.int64)
+    for s in range(n):
+        fin = np.isfinite(d[s])
+        dag = int(np.sum(fin[src] & fin[col] & (d[s][col] == d[s][src] + 1)))
+        want = [int(fin.sum()), int(outdeg[fin].sum()), dag, int(d[s][fin].max()) + 1]
+        check("counters", stats[s].tolist() == want)
     return sorted(set(fails))
 
 
