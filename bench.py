@@ -1,21 +1,22 @@
 #!/usr/bin/env python
 """Benchmark of the Brandes betweenness-centrality hot path on one MI355X.
 
-Default workload: directed R-MAT graph, scale 16 (n = 65,536), edge factor 16, quadrant
-split (0.57, 0.19, 0.19, 0.05), self-loops and repeated pairs removed, seed 16; exact BC
-from all 65,536 sources, FP64 output, uint64 path counts.  One step = one exact BC pass
-(every source: forward sweep, backward sweep, accumulation) with the graph already
-resident in HBM.
+Default workload: directed R-MAT graph, scale 20 (n = 1,048,576), edge factor 16, quadrant
+split (0.57, 0.19, 0.19, 0.05), self-loops and repeated pairs removed, seed 20; BC from 1,024
+sources drawn uniformly without replacement (seed 2020), FP64 output, exact path counts.  One
+step = one sampled-BC pass over those sources (forward sweep, backward sweep, accumulation for
+each) with the graph already resident in HBM.  The same run also times the 1024 x 1024 lattice
+with random edge orientation (1,024 sources) and reports it under `extra.lattice`.
 
 Prints one JSON line: nominal GTEPS (sources x edges / s) as `value`, the roofline of the
 search kernel (algorithmic bytes from exact per-call work counters over the kernel's
-HIP-event time), and the CPU oracle timed on a bounded sample of the same sources.
+HIP-event time, against the 8 TB/s peak and against the bandwidth a STREAM-style kernel
+reaches on the same GPU), and the CPU oracle timed on the same sources.
 
-Other workloads (--workload): rmat20 (scale 20, edge factor 16, 1,024 seeded sources),
-lattice (1024 x 1024 lattice with random edge orientation, 1,024 seeded sources), batch
-(4,096 R-MAT graphs of scale 6..12, edge factor 8, exact BC of each in one launch), serve
-(Poisson request stream), paper (the paper's three strategies against the default path on
-BA digraphs).
+Other workloads (--workload): rmat16 (scale 16, edge factor 16, exact BC from all 65,536
+sources), lattice (the lattice alone), batch (4,096 R-MAT graphs of scale 6..12, edge factor 8,
+exact BC of each in one launch), serve (Poisson request stream), paper (the paper's three
+strategies against the default path on BA digraphs).
 """
 from __future__ import annotations
 
@@ -104,9 +105,14 @@ def _time_oracle(oracle, g, sources, m, threads, budget_s):
 
 
 def cpu_baseline(n, u, v, sources, m, budget_s):
-    """The CPU oracle, untuned, on a bounded prefix of the benchmark's sources: all host
-    threads, and one thread on a smaller prefix (a quarter of the budget)."""
+    """The CPU oracle, untuned, built -O3 -march=native on this host, on a bounded prefix of the
+    benchmark's sources (all of them when they fit the budget): all host threads, and one
+    thread on a smaller prefix (a quarter of the budget)."""
     import oracle
+    try:
+        lib = os.path.basename(oracle.use_native(True))
+    except Exception as e:   # no compiler on this host: the generic -O3 build
+        lib = f"{os.path.basename(oracle.use_native(False))} (native build failed: {e})"
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
     threads = max(1, min(threads, oracle.max_threads() if oracle.max_threads() > 0 else threads))
     g = oracle.Graph(n, u, v)
@@ -114,30 +120,49 @@ def cpu_baseline(n, u, v, sources, m, budget_s):
     val1, k1, dt1 = _time_oracle(oracle, g, sources, m, 1, budget_s / 4)
     return {"value": val, "unit": "GTEPS", "cores": threads, "kind": "oracle",
             "sample": f"{k} of the {len(sources)} sources (first {k} in benchmark order), "
-                      f"{dt:.1f} s on {threads} threads of {cpu_info()}",
+                      f"{dt:.1f} s on {threads} threads of {cpu_info()}, {lib}",
             "single_thread": {"value": val1, "unit": "GTEPS", "cores": 1,
                               "sample": f"first {k1} sources, {dt1:.1f} s on 1 thread"}}
 
 
-def bench_single(args, torch, bcmi, gg):
-    if args.workload == "rmat16":
+def stream_achievable(bcmi, sizes_gib=(1, 2, 4), reps=5):
+    """Median copy and triad GB/s of the in-tree STREAM-style kernels at several array sizes
+    (all far above the 256 MB MALL); `achievable` is the best of those medians."""
+    runs = []
+    for gib in sizes_gib:
+        c, t = bcmi.bc_stream_probe(int(gib) << 30, reps)
+        runs.append({"array_gib": gib, "copy_gbs": c, "triad_gbs": t})
+    best = max(max(r["copy_gbs"], r["triad_gbs"]) for r in runs)
+    return best, runs
+
+
+WORKLOADS = {
+    "rmat16": dict(cfg={"workload": "rmat16-exact", "graph": "R-MAT scale 16, edge factor 16, a=0.57 b=0.19 "
+                        "c=0.19 d=0.05, seed 16, self-loops and duplicates removed", "sources": "all"}),
+    "rmat20": dict(cfg={"workload": "rmat20-sampled1024", "graph": "R-MAT scale 20, edge factor 16, a=0.57 "
+                        "b=0.19 c=0.19 d=0.05, seed 20, self-loops and duplicates removed",
+                        "sources": "1024 uniform without replacement, seed 2020"}),
+    "lattice": dict(cfg={"workload": "lattice1024-sampled1024", "graph": "1024x1024 lattice, random edge "
+                         "orientation, seed 1", "sources": "1024 uniform without replacement, seed 1024"}),
+}
+
+
+def workload_input(gg, name):
+    """(n, src, dst, sources, exact) of a single-graph workload."""
+    if name == "rmat16":
         n, u, v = gg.rmat(16, 16, 16)
-        sources = np.arange(n, dtype=np.uint32)
-        exact = True
-        cfg = {"workload": "rmat16-exact", "graph": "R-MAT scale 16, edge factor 16, a=0.57 b=0.19 c=0.19 "
-               "d=0.05, seed 16, self-loops and duplicates removed", "sources": "all"}
-    elif args.workload == "rmat20":
+        return n, u, v, np.arange(n, dtype=np.uint32), True
+    if name == "rmat20":
         n, u, v = gg.rmat(20, 16, 20)
-        sources = gg.uniform_sources(n, 1024, 2020)
-        exact = False
-        cfg = {"workload": "rmat20-sampled1024", "graph": "R-MAT scale 20, edge factor 16, seed 20",
-               "sources": "1024 uniform without replacement, seed 2020"}
-    else:
-        n, u, v = gg.grid_random_orientation(1024, 1024, 1)
-        sources = gg.uniform_sources(n, 1024, 1024)
-        exact = False
-        cfg = {"workload": "lattice1024-sampled1024", "graph": "1024x1024 lattice, random edge orientation, "
-               "seed 1", "sources": "1024 uniform without replacement, seed 1024"}
+        return n, u, v, gg.uniform_sources(n, 1024, 2020), False
+    n, u, v = gg.grid_random_orientation(1024, 1024, 1)
+    return n, u, v, gg.uniform_sources(n, 1024, 1024), False
+
+
+def time_single(args, torch, bcmi, gg, name, achievable):
+    """W untimed steps, then exactly K timed steps of one single-graph workload."""
+    n, u, v, sources, exact = workload_input(gg, name)
+    cfg = dict(WORKLOADS[name]["cfg"])
     t0 = time.perf_counter()
     g = bcmi.bc_build_csr(n, u, v)
     torch.cuda.synchronize()
@@ -179,21 +204,18 @@ def bench_single(args, torch, bcmi, gg):
     inf = infos[-1]
     nbytes = algorithmic_bytes(inf, n)
     achieved = nbytes / (kernel_ms / 1e3) / 1e9
-    traffic = load_traffic(cfg["workload"], 1)
+    # the per-source accounting 16|E_s| + 32|D_s| + 92|R_s| summed over sources, whatever the
+    # path: what one source at a time would move (a 64-source batch shares its edge reads)
+    per_source = (16 * inf["examined"] + 32 * inf["dag_edges"] + 92 * inf["reached"]) / (kernel_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(cfg["workload"], 1),
+            "achievable": achievable, "frac_of_achievable": achieved / achievable if achievable else None,
+            "kernel": ["k_bc_global", "k_bc_lds", "k_msb", "k_bc_narrow"][inf["path"]],
+            "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": nbytes,
+            "per_source_convention_gbs": per_source}
     res = {
-        "metric": "GTEPS (sources x edges / s), nominal, exact/sampled BC",
-        "value": k * g.m / (ms_per_step / 1e3) / 1e9,
-        "unit": "GTEPS",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32+f64" if inf["path"] == 2 else "u64+f64",
-        "data": "synthetic",
-        "config": cfg,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ["k_bc_global", "k_bc_lds", "k_msb", "k_bc_narrow"][inf["path"]],
-                     "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": nbytes},
+        "value": k * g.m / (ms_per_step / 1e3) / 1e9, "ms_per_step": ms_per_step,
+        "dtype": "u32+f64" if inf["path"] == 2 else "u64+f64", "config": cfg, "roofline": roof,
         "extra": {
             "traversed_gteps": inf["examined"] / (ms_per_step / 1e3) / 1e9,
             "build_csr_ms": build_ms,
@@ -203,10 +225,6 @@ def bench_single(args, torch, bcmi, gg):
             "path": ["global", "lds", "batched", "narrow"][inf["path"]], "tuning": tune,
             "batch_entries": inf["batch_entries"], "batch_edge_visits": inf["batch_edge_visits"],
             "batch_scans": inf["batch_scans"], "batch_handoffs": inf["batch_handoffs"],
-            # the per-source accounting 16|E_s| + 32|D_s| + 92|R_s| summed over sources, whatever
-            # the path: what one source at a time would move (batches share their edge reads)
-            "per_source_convention_gbs": (16 * inf["examined"] + 32 * inf["dag_edges"] + 92 * inf["reached"])
-            / (kernel_ms / 1e3) / 1e9,
             "batch_cycles_fwd_bwd_reset": inf["batch_cycles"],
             "kernel_ms_all": [i["kernel_ms"] for i in infos],
         },
@@ -215,10 +233,33 @@ def bench_single(args, torch, bcmi, gg):
         per = one_source_per_launch_ms(bcmi, torch, g, sources, 256)
         res["extra"]["one_launch_per_source_ms_estimated"] = per * k
         res["extra"]["speedup_vs_launch_per_source"] = per * k / ms_per_step
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(n, u, v, sources, g.m, args.cpu_seconds)
     g.free()
-    return res
+    return res, (n, u, v, sources, g.m)
+
+
+def bench_single(args, torch, bcmi, gg):
+    achievable, probe = (None, None)
+    if not args.no_stream_probe:
+        achievable, probe = stream_achievable(bcmi)
+    res, (n, u, v, sources, m) = time_single(args, torch, bcmi, gg, args.workload, achievable)
+    line = {
+        "metric": "GTEPS (sources x edges / s), nominal, exact/sampled BC",
+        "value": res["value"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": res["dtype"], "data": "synthetic", "config": res["config"], "roofline": res["roofline"],
+        "extra": res["extra"],
+    }
+    line["extra"]["stream_probe"] = probe
+    if args.workload == "rmat20" and not args.no_lattice:
+        lat, _ = time_single(args, torch, bcmi, gg, "lattice", achievable)
+        line["extra"]["lattice"] = {"value_gteps": lat["value"], "ms_per_step": lat["ms_per_step"],
+                                    "config": lat["config"], "roofline": lat["roofline"],
+                                    "sources": lat["extra"]["sources"], "levels_max": lat["extra"]["levels_max"],
+                                    "sigma_fp64_fallback_sources": lat["extra"]["sigma_fp64_fallback_sources"],
+                                    "path": lat["extra"]["path"], "kernel_ms_all": lat["extra"]["kernel_ms_all"]}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, u, v, sources, m, args.cpu_seconds)
+    return line
 
 
 def one_source_per_launch_ms(bcmi, torch, g, sources, reps):
@@ -408,7 +449,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat16",
+    ap.add_argument("--workload", default="rmat20",
                     choices=["rmat16", "rmat20", "lattice", "batch", "serve", "paper"])
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="mean arrivals per second")
@@ -417,6 +458,9 @@ def main():
     ap.add_argument("--strategy", default="auto", choices=["auto", "batched", "per-source"])
     ap.add_argument("--knob", action="append", default=[], help="launch knob override, e.g. batch_wg_size=512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lattice", action="store_true", help="rmat20 workload: skip the lattice leg")
+    ap.add_argument("--no-stream-probe", action="store_true",
+                    help="skip the STREAM-style bandwidth probe (roofline.achievable is then null)")
     ap.add_argument("--skip-compare", action="store_true",
                     help="batch workload: skip the one-launch-per-graph / per-source comparisons")
     ap.add_argument("--plain-baseline", action="store_true",

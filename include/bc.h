@@ -142,7 +142,18 @@ BC_API bc_status bc_exact(bc_graph g, double* d_bc, const bc_tuning* t, void* st
 BC_API bc_status bc_sampled(bc_graph g, const uint32_t* d_sources, int32_t k, double* d_bc,
                      const bc_tuning* t, void* stream, bc_info* info);
 
-/* One source, for inspection: distances and path counts exactly as the forward sweep
+/* BC as bc_sampled (k >= 0) or bc_exact (k < 0 with d_sources NULL), also reporting which
+ * sources needed the double-precision recount.  Section II-D keeps path counts in 4-byte
+ * integers and is silent on overflow; here a source overflows when one of its shortest-path
+ * counts exceeds 2^64-1, which is detected exactly (carry out of the 64-bit addition).
+ * d_overflowed: n bytes (device), overwritten: 1 at the id of every source of the call whose
+ * counts overflowed, 0 everywhere else.  A source listed several times is flagged once.  Other
+ * arguments, errors and stream semantics as bc_sampled. */
+BC_API bc_status bc_sampled_flags(bc_graph g, const uint32_t* d_sources, int32_t k, double* d_bc,
+                                  uint8_t* d_overflowed, const bc_tuning* t, void* stream, bc_info* info);
+
+/* One source, for inspection (section I: the BFS distances d(s,.) and shortest-path counts
+ * sigma(s,.) of the forward sweep, and the dependencies delta_s(.) of the backward sweep): distances and path counts exactly as the forward sweep
  * leaves them, and the dependencies of the backward sweep.  d_dist (int32 n),
  * d_sigma_u64 (uint64 n; exact counts, all 0 when overflowed), d_sigma_f64 (double n;
  * counts as doubles, the double-precision recount when overflowed), d_delta (double n;
@@ -218,6 +229,14 @@ BC_API bc_status bc_serve_poll(bc_server s, uint64_t ticket, bc_info* info);
 
 /* Stop the server: queued requests are cancelled, running ones are finished first. */
 BC_API bc_status bc_serve_destroy(bc_server s);
+
+/* Measurement utility, not part of the method: the HBM bandwidth that plain streaming reaches
+ * on the current device.  STREAM-style copy (b = a) and triad (a = b + q c) over arrays of
+ * `bytes` each (choose far more than the 256 MB MALL), timed with HIP events, median of `reps`
+ * runs after one warm-up run.  Writes GB/s counting 2 (copy) or 3 (triad) array sizes moved per
+ * run into the non-NULL host outputs.  Allocates and frees three device arrays; synchronous.
+ * Errors: BC_E_INVAL (bytes < 16, reps < 1), BC_E_NOMEM, BC_E_HIP. */
+BC_API bc_status bc_stream_probe(size_t bytes, int32_t reps, double* h_copy_gbs, double* h_triad_gbs);
 
 /* Thread-local message of the last error on this thread ("" if none). */
 BC_API const char* bc_last_error(void);

@@ -6,8 +6,10 @@ built library is missing; there is no fallback implementation.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import torch
@@ -69,6 +71,8 @@ def lib():
         L.bc_graph_free.argtypes = [P]
         L.bc_exact.argtypes = [P, P, ctypes.POINTER(bc_tuning), P, ctypes.POINTER(bc_info)]
         L.bc_sampled.argtypes = [P, P, ctypes.c_int32, P, ctypes.POINTER(bc_tuning), P, ctypes.POINTER(bc_info)]
+        L.bc_sampled_flags.argtypes = [P, P, ctypes.c_int32, P, P, ctypes.POINTER(bc_tuning), P,
+                                       ctypes.POINTER(bc_info)]
         L.bc_sssp.argtypes = [P, ctypes.c_uint32, P, P, P, P, ctypes.POINTER(ctypes.c_int32), P]
         L.bc_batch.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(bc_tuning), P,
                                ctypes.POINTER(bc_info)]
@@ -80,14 +84,16 @@ def lib():
         L.bc_approx_vertex.argtypes = [P, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P,
                                        ctypes.c_int32, P]
+        L.bc_stream_probe.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
         L.bc_serve_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(P)]
         L.bc_serve_submit.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_uint64)]
         L.bc_serve_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(bc_info)]
         L.bc_serve_destroy.argtypes = [P]
         for name in ["bc_build_csr", "bc_graph_info", "bc_graph_arrays", "bc_graph_order", "bc_graph_free", "bc_exact",
-                     "bc_sampled",
+                     "bc_sampled", "bc_sampled_flags",
                      "bc_sssp", "bc_batch", "bc_tune", "bc_paper_strategy", "bc_approx", "bc_approx_vertex",
-                     "bc_serve_create", "bc_serve_submit", "bc_serve_poll", "bc_serve_destroy"]:
+                     "bc_serve_create", "bc_serve_submit", "bc_serve_poll", "bc_serve_destroy", "bc_stream_probe"]:
             getattr(L, name).restype = ctypes.c_int32
         L.bc_last_error.restype = ctypes.c_char_p
         L.bc_version.restype = ctypes.c_char_p
@@ -127,6 +133,29 @@ def tuning(**kw):
     return t
 
 
+# Handles still alive at interpreter exit are released by an exit hook, which runs before the C
+# runtime's own exit handlers (a profiler's among them): the library then makes no HIP call
+# once those have torn down.
+_live_graphs = weakref.WeakSet()
+_live_servers = weakref.WeakSet()
+
+
+def _release_all():
+    for s in list(_live_servers):
+        try:
+            s.destroy()
+        except Exception:
+            pass
+    for g in list(_live_graphs):
+        try:
+            g.free()
+        except Exception:
+            pass
+
+
+atexit.register(_release_all)
+
+
 class Graph:
     """Owning wrapper of a bc_graph handle."""
 
@@ -134,6 +163,7 @@ class Graph:
         self.handle = handle
         self.n = n
         self.m = m
+        _live_graphs.add(self)
 
     def free(self):
         if self.handle:
@@ -225,6 +255,24 @@ def bc_sampled(g: Graph, sources, out=None, tuning=None, stream=None, info=False
     return (out, inf.as_dict()) if info else out
 
 
+def bc_sampled_flags(g: Graph, sources=None, out=None, flags=None, tuning=None, stream=None, info=False):
+    """BC over `sources` (None: every vertex, exact) plus the per-source overflow flags: a uint8
+    tensor of n entries, 1 at every source whose path counts exceeded 2^64 - 1."""
+    out = _out(g, out)
+    if flags is None:
+        flags = torch.empty(g.n, dtype=torch.uint8, device="cuda")
+    assert flags.dtype == torch.uint8 and flags.numel() >= g.n and flags.is_contiguous()
+    srcs = _dev_u32(sources) if sources is not None else None
+    k = srcs.numel() if srcs is not None else -1
+    inf = bc_info() if info else None
+    _check(lib().bc_sampled_flags(g.handle, P(srcs.data_ptr()) if srcs is not None and srcs.numel() else None, k,
+                                  P(out.data_ptr()), P(flags.data_ptr()), ctypes.byref(tuning) if tuning else None,
+                                  _stream(stream), ctypes.byref(inf) if inf is not None else None))
+    if not info and srcs is not None:
+        _check_keepalive(srcs, stream)
+    return (out, flags, inf.as_dict()) if info else (out, flags)
+
+
 def bc_paper_strategy(g: Graph, strategy: int, wg_size: int = 256, sources=None, out=None, stream=None,
                       info=False):
     """One of the paper's three GPU strategies (1 vertex-parallel, 2 edge-parallel, 3 host-
@@ -307,7 +355,7 @@ def bc_tune(g: Graph) -> dict:
     return {k: getattr(t, k) for k, _ in bc_tuning._fields_}
 
 
-@dataclass
+@dataclass(eq=False)
 class Server:
     handle: object
 
@@ -320,7 +368,9 @@ class Server:
 def bc_serve_create(hbm_budget_bytes: int, max_slots: int = 0) -> Server:
     h = P()
     _check(lib().bc_serve_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)))
-    return Server(h)
+    s = Server(h)
+    _live_servers.add(s)
+    return s
 
 
 def bc_serve_submit(server: Server, g: Graph, sources, out) -> int:
@@ -344,6 +394,13 @@ def bc_serve_poll(server: Server, ticket: int):
 
 def bc_serve_destroy(server: Server):
     server.destroy()
+
+
+def bc_stream_probe(nbytes: int, reps: int = 5):
+    """(copy GB/s, triad GB/s) of STREAM-style kernels over arrays of `nbytes` each."""
+    c, t = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().bc_stream_probe(int(nbytes), int(reps), ctypes.byref(c), ctypes.byref(t)))
+    return c.value, t.value
 
 
 def version() -> str:

@@ -3,6 +3,7 @@
 #include "bc_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include <cstdio>
@@ -15,12 +16,20 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 
 void graph_scratch_free(Graph& g);
+void batch_forget_graph(const Graph* g);
+
+Graph::Graph() {
+    static std::atomic<uint64_t> next{1};
+    uid = next.fetch_add(1);
+}
 
 Graph::~Graph() {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(device);
     (void)hipDeviceSynchronize();
+    // a cached batch plan that lists this graph would replay its freed arrays
+    batch_forget_graph(this);
     graph_scratch_free(*this);
     strat_pool_delete(strat);
     if (row_ptr) (void)hipFree(row_ptr);
@@ -219,6 +228,32 @@ bc_status bc_sampled(bc_graph gh, const uint32_t* d_sources, int32_t k, double* 
         if (info) {
             const double ms = tm.stop_ms();
             fill_info(*g, st, path, ms, (uint32_t)k, info);
+        }
+    });
+}
+
+bc_status bc_sampled_flags(bc_graph gh, const uint32_t* d_sources, int32_t k, double* d_bc, uint8_t* d_overflowed,
+                           const bc_tuning* t, void* stream, bc_info* info) {
+    return guarded([&] {
+        Graph* g = as_graph(gh);
+        BC_REQUIRE(d_bc != nullptr, BC_E_INVAL, "null output array");
+        BC_REQUIRE(d_overflowed != nullptr, BC_E_INVAL, "null overflow-flag array");
+        BC_REQUIRE(k >= 0 || d_sources == nullptr, BC_E_INVAL, "k < 0 (every vertex) takes no source array");
+        BC_REQUIRE(k <= 0 || d_sources != nullptr, BC_E_INVAL, "null source array");
+        std::lock_guard<std::mutex> lk(g->mu);
+        const hipStream_t st = (hipStream_t)stream;
+        const Knobs kn = resolve_knobs(*g, t);
+        RunArgs ra{};
+        ra.g = g;
+        ra.sources = k < 0 ? nullptr : d_sources;
+        ra.num_items = k < 0 ? (uint32_t)g->n : (uint32_t)k;
+        ra.bc = d_bc;
+        ra.ovf_flags = d_overflowed;
+        StreamTimer tm(st, info != nullptr);
+        const int path = run_sources(ra, kn, st, *g);
+        if (info) {
+            const double ms = tm.stop_ms();
+            fill_info(*g, st, path, ms, ra.num_items, info);
         }
     });
 }
@@ -436,6 +471,10 @@ bc_status bc_paper_strategy(bc_graph gh, int32_t strategy, int32_t wg_size, cons
             *info = out;
         }
     });
+}
+
+bc_status bc_stream_probe(size_t bytes, int32_t reps, double* h_copy_gbs, double* h_triad_gbs) {
+    return guarded([&] { stream_probe(bytes, reps, h_copy_gbs, h_triad_gbs); });
 }
 
 bc_status bc_tune(bc_graph gh, bc_tuning* out) {

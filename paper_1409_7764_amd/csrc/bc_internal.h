@@ -86,7 +86,11 @@ struct Knobs {
 
 // Graph handle (the opaque bc_graph).
 struct Graph {
+    Graph();
     int device = 0;
+    // identity that is never reused within the process (a handle's address can be, once it is
+    // freed): cached launch plans are keyed by it
+    uint64_t uid = 0;
     int32_t n = 0;
     uint32_t m = 0;
     uint32_t* row_ptr = nullptr;   // n+1
@@ -141,6 +145,7 @@ struct RunArgs {
     const uint32_t* sources;   // nullable: item i is source i
     uint32_t num_items;
     double* bc;                // nullable (bc_sssp)
+    uint8_t* ovf_flags = nullptr;   // nullable: per-source overflow flags by caller id (n bytes)
     // optional export of one source's arrays (bc_sssp)
     int32_t* ex_dist = nullptr;
     uint64_t* ex_sigma = nullptr;
@@ -162,6 +167,8 @@ struct WorkDesc {
     const uint32_t* perm;      // nullable: caller id -> kernel id, applied to `sources`
     const uint32_t* iperm;     // nullable: kernel id -> caller id, applied to every output index
     uint32_t* counters;        // nullable: per-descriptor {done, overflowed, levels_max, bad}
+    uint8_t* ovf_flags;        // nullable: n bytes by caller id, 1 where a source of the launch was
+                               // recounted in double precision (zeroed with the BC output)
     int32_t n;
     uint32_t max_in;           // largest in-degree (bounds the counts; 0 = unknown)
     uint32_t item_begin;       // first work item of this descriptor in the launch
@@ -211,6 +218,9 @@ struct LaunchPlan {
 };
 
 LaunchPlan make_plan(const Knobs& k, uint32_t max_n, uint32_t items, int device);
+WorkDesc single_graph_desc(const Graph& g, const RunArgs& ra);
+void store_desc(WorkDesc* dst, const WorkDesc& d, hipStream_t st);
+void reset_slot_records(VRec* rec, size_t count, hipStream_t st);
 void enqueue_plan(const LaunchPlan& p, hipStream_t st, uint32_t max_n);
 void pool_ensure(SlotPool& p, uint32_t slot_n, int slots, hipStream_t st);
 void pool_free(SlotPool& p);
@@ -251,6 +261,9 @@ void draw_pivots(uint64_t seed, uint32_t n, uint32_t k, uint32_t* out);   // Spl
 uint32_t hoeffding_pivots(uint32_t n, double eps, double delta);        // n when the bound needs >= n
 void scale_bc(double* d_bc, uint32_t n, double f, hipStream_t st);
 double read_bc_entry(const double* d_bc, uint32_t v, double* d_tmp, hipStream_t st);
+
+// ---- STREAM-style bandwidth probe (stream_probe.hip) -------------------------------------------
+void stream_probe(size_t bytes, int reps, double* copy_gbs, double* triad_gbs);
 
 // ---- tuning (tune.hip) -------------------------------------------------------------------
 Knobs resolve_knobs(Graph& g, const bc_tuning* t);

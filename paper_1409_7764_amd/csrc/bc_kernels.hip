@@ -649,6 +649,7 @@ __device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s,
         atomicAdd(&a.stats->n_done, 1u);
         if (f64) atomicAdd(&a.stats->n_overflow, 1u);
         atomicMax(&a.stats->levels_max, (uint32_t)nlev);
+        if (f64 && D.ovf_flags) D.ovf_flags[D.iperm ? D.iperm[s] : s] = 1;
         if (D.counters) {
             if (f64) atomicAdd(&D.counters[1], 1u);
             atomicMax(&D.counters[2], (uint32_t)nlev);
@@ -739,8 +740,12 @@ __global__ void k_prepare(const WorkDesc* descs, uint32_t ndesc, CallStats* stat
     for (uint32_t d = blockIdx.y; d < ndesc; d += gridDim.y) {
         if (blockIdx.x == 0 && threadIdx.x < 4 && descs[d].counters) descs[d].counters[threadIdx.x] = 0u;
         double* bc = descs[d].bc;
+        uint8_t* fl = descs[d].ovf_flags;
         const uint32_t n = (uint32_t)descs[d].n;
-        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) bc[i] = 0.0;
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            bc[i] = 0.0;
+            if (fl) fl[i] = 0;
+        }
     }
 }
 
@@ -961,6 +966,7 @@ struct RetryCtx {
     GraphScratch* gs;
     Knobs k;
     double* bc;
+    uint8_t* ovf_flags;
 };
 
 // `kernel_ids`: the list holds ids of the relabelled copy (else caller ids)
@@ -981,6 +987,7 @@ static void retry_launch(void* ctx, const uint32_t* list, const uint32_t* count,
     d.row_ptr = g.krow();
     d.col = g.kcol();
     d.bc = c.bc;
+    d.ovf_flags = c.ovf_flags;
     d.sources = list;
     d.perm = kernel_ids ? nullptr : g.perm;
     d.iperm = g.iperm;
@@ -1026,20 +1033,16 @@ static bool want_narrow(const Knobs& k, const Graph&) {
     return false;
 }
 
-int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
-    GraphScratch& gs = scratch_of(g);
-    const bool exporting = ra.ex_dist || ra.ex_sigma || ra.ex_sigma_f || ra.ex_delta;
-    if (!exporting && want_narrow(k, g)) return run_narrow(ra, k, st, g);
-    if (!exporting && want_batched(k, g, ra.num_items)) return run_batched(ra, k, st, g);
-    if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
-    if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
-    // Deep graphs keep the caller's numbering: a lattice-like graph's own ids put a frontier's
-    // neighbours in shared cache lines, which the in-degree relabelling would scatter.
+// Descriptor of a one-source-per-workgroup launch over one graph.  Deep graphs keep the
+// caller's numbering: a lattice-like graph's own ids put a frontier's neighbours in shared cache
+// lines, which the in-degree relabelling would scatter.
+WorkDesc single_graph_desc(const Graph& g, const RunArgs& ra) {
     const bool own_ids = g.deep;
     WorkDesc d{};
     d.row_ptr = own_ids ? g.row_ptr : g.krow();
     d.col = own_ids ? g.col : g.kcol();
     d.bc = ra.bc;
+    d.ovf_flags = ra.ovf_flags;
     d.sources = ra.sources;
     d.perm = own_ids ? nullptr : g.perm;
     d.iperm = own_ids ? nullptr : g.iperm;
@@ -1048,6 +1051,38 @@ int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     d.max_in = g.max_in_degree;
     d.item_begin = 0;
     d.num_items = ra.num_items;
+    return d;
+}
+
+namespace {
+__global__ void k_store_desc(WorkDesc* dst, WorkDesc d) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = d;
+}
+}  // namespace
+
+// Writes a descriptor into device memory in stream order, from a kernel argument (no host
+// staging buffer).
+void store_desc(WorkDesc* dst, const WorkDesc& d, hipStream_t st) {
+    hipLaunchKernelGGL(k_store_desc, dim3(1), dim3(64), 0, st, dst, d);
+    BC_HIP_TRY(hipGetLastError());
+}
+
+// Every record of `count` slot entries back to unreached (distance -1, count 0).
+void reset_slot_records(VRec* rec, size_t count, hipStream_t st) {
+    if (!count) return;
+    hipLaunchKernelGGL(k_fill_rec, dim3((unsigned)std::min<size_t>((count + 255) / 256, 65536)), dim3(256), 0, st,
+                       rec, count);
+    BC_HIP_TRY(hipGetLastError());
+}
+
+int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
+    GraphScratch& gs = scratch_of(g);
+    const bool exporting = ra.ex_dist || ra.ex_sigma || ra.ex_sigma_f || ra.ex_delta;
+    if (!exporting && want_narrow(k, g)) return run_narrow(ra, k, st, g);
+    if (!exporting && want_batched(k, g, ra.num_items)) return run_batched(ra, k, st, g);
+    if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
+    if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
+    const WorkDesc d = single_graph_desc(g, ra);
     BC_HIP_TRY(hipMemcpyAsync(gs.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
 
     LaunchPlan p = make_plan(k, (uint32_t)g.n, ra.num_items, g.device);
@@ -1080,13 +1115,14 @@ int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     d.row_ptr = g.krow();
     d.col = g.kcol();
     d.bc = ra.bc;
+    d.ovf_flags = ra.ovf_flags;
     d.perm = g.perm;
     d.iperm = g.iperm;
     d.n = g.n;
     d.max_in = g.max_in_degree;
     d.num_items = ra.num_items;
     BC_HIP_TRY(hipMemcpyAsync(gs.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
-    // zero BC and the call counters
+    // zero BC, the flags and the call counters
     LaunchPlan z;
     z.args.descs = gs.desc;
     z.args.ndesc = 1;
@@ -1095,7 +1131,7 @@ int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     z.args.zero_outputs = 1;
     z.grid = 0;
     enqueue_plan(z, st, (uint32_t)g.n);
-    RetryCtx rc{&g, &gs, k, ra.bc};
+    RetryCtx rc{&g, &gs, k, ra.bc, ra.ovf_flags};
     run_msb_enqueue(*gs.msb, g, ra.sources, ra.num_items, ra.bc, g.stats, k.batch_wg, k.team, k.teams, st,
                     retry_launch, &rc);
     return 2;
@@ -1121,7 +1157,7 @@ int run_narrow(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     z.args.zero_outputs = 1;
     z.grid = 0;
     enqueue_plan(z, st, (uint32_t)g.n);
-    RetryCtx rc{&g, &gs, k, ra.bc};
+    RetryCtx rc{&g, &gs, k, ra.bc, ra.ovf_flags};
     run_narrow_enqueue(*gs.narrow, g, ra.sources, ra.num_items, ra.bc, g.stats, k.teams, st, retry_launch, &rc);
     return 3;
 }
@@ -1146,6 +1182,7 @@ void read_stats(Graph& g, hipStream_t st, CallStats* out) {
 struct BatchPlan {
     int device = 0;
     std::vector<const Graph*> graphs;
+    std::vector<uint64_t> uids;       // the graphs' identities (addresses can be reused)
     std::vector<double*> outs;
     Knobs knobs;
     WorkDesc* d_descs = nullptr;      // [ndesc]
@@ -1173,9 +1210,16 @@ struct BatchPlan {
         if (k.wg_size != knobs.wg_size || k.hub != knobs.hub || k.lds_max_n != knobs.lds_max_n ||
             k.teams != knobs.teams || k.use_graph != knobs.use_graph)
             return false;
-        for (int i = 0; i < num; ++i)
-            if ((const Graph*)gs[i] != graphs[i] || bcs[i] != outs[i]) return false;
+        for (int i = 0; i < num; ++i) {
+            const Graph* g = (const Graph*)gs[i];
+            if (g != graphs[i] || g->uid != uids[i] || bcs[i] != outs[i]) return false;
+        }
         return true;
+    }
+    bool lists(const Graph* g) const {
+        for (size_t i = 0; i < graphs.size(); ++i)
+            if (graphs[i] == g && uids[i] == g->uid) return true;
+        return false;
     }
 };
 
@@ -1186,10 +1230,13 @@ static void enqueue_batch(BatchPlan& bp, hipStream_t st) {
     for (int c = 0; c < bp.nclass; ++c) enqueue_plan(bp.lp[c], st, bp.maxn[c]);
 }
 
-void batch_release_all() {
+// Called when a graph handle is freed: a plan that lists it is dropped before its arrays go.
+void batch_forget_graph(const Graph* g) {
     std::lock_guard<std::mutex> lk(g_batch_mu);
-    delete g_batch_plan;
-    g_batch_plan = nullptr;
+    if (g_batch_plan && g_batch_plan->lists(g)) {
+        delete g_batch_plan;
+        g_batch_plan = nullptr;
+    }
 }
 
 static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* bcs, const Knobs& k, int dev,
@@ -1200,6 +1247,7 @@ static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* b
         bp->knobs = k;
         for (int i = 0; i < num; ++i) {
             bp->graphs.push_back((const Graph*)gs[i]);
+            bp->uids.push_back(((const Graph*)gs[i])->uid);
             bp->outs.push_back(bcs[i]);
         }
         // class 0: LDS-resident graphs, class 1: the rest; each class largest work first

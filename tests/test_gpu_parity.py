@@ -34,6 +34,18 @@ def np_of(t):
     return t.detach().cpu().numpy()
 
 
+def check_overflow_set(flags, S, ovf, n):
+    """The device's per-source overflow flags (bytes by vertex id) against the oracle's
+    per-item flags over the source list S (None = every vertex): the same set of ids."""
+    got = np_of(flags).astype(np.int64)
+    want = np.zeros(n, np.int64)
+    ids = np.arange(n) if S is None else np.asarray(S, np.int64)
+    want[ids[np.asarray(ovf, bool)]] = 1
+    assert got.shape == (n,)
+    diff = np.nonzero(got != want)[0]
+    assert diff.size == 0, f"overflow sets differ at {diff.size} ids (first {diff[:5].tolist()})"
+
+
 # ---------------------------------------------------------------------------------------
 # a1: CSR / CSC builder
 # ---------------------------------------------------------------------------------------
@@ -279,6 +291,9 @@ def test_overflow_diamond_chain(bc, k):
         assert info["path"] == PATH_CODE[path]
         assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
         rel_close(np_of(got), want, what=f"bc {path}")
+        got, flags, info = bc.bc_sampled_flags(g, tuning=force(bc, path), info=True)
+        check_overflow_set(flags, None, ovf, n)
+        rel_close(np_of(got), want, what=f"bc {path} (flags)")
     g.free()
 
 
@@ -293,7 +308,16 @@ def test_overflow_grid_dag(bc):
         got, info = bc.bc_exact(g, tuning=force(bc, path), info=True)
         assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
         rel_close(np_of(got), want, what=f"bc {path}")
-    # the overflowing source set itself, one source at a time
+        # the overflowing source set itself, every source
+        got, flags, info = bc.bc_sampled_flags(g, tuning=force(bc, path), info=True)
+        check_overflow_set(flags, None, ovf, n)
+        rel_close(np_of(got), want, what=f"bc {path} (flags)")
+    # a multiset: repeated sources are flagged once, counted twice
+    S = np.array([0, 0, 1, 36, 36, 1224, 70], np.uint32)
+    want_s, ovf_s, _ = oracle.bc(o, S)
+    got, flags = bc.bc_sampled_flags(g, S)
+    check_overflow_set(flags, S, ovf_s, n)
+    rel_close(np_of(got), want_s, what="bc multiset (flags)")
     for s in [0, 1, 35, 36, 70]:
         assert bc.bc_sssp(g, s)["overflow"] == bool(oracle.brandes_source(o, s)["overflow"])
     g.free()
@@ -333,6 +357,8 @@ def test_high_diameter_lattice(bc):
         assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
         assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
         rel_close(np_of(got), want, what="bc")
+        _, flags = bc.bc_sampled_flags(g, tuning=force(bc, path))
+        check_overflow_set(flags, None, ovf, n)
     g.free()
 
 
@@ -532,7 +558,8 @@ def test_rmat_scale20_sampled_subset(bc):
     g = bc.bc_build_csr(n, u, v)
     S = gg.uniform_sources(n, 1024, 2020)
     say("rmat20 sampled 1024")
-    allk, info = bc.bc_sampled(g, S, info=True)
+    allk, flags, info = bc.bc_sampled_flags(g, S, info=True)
+    assert int(np_of(flags).sum()) == 0
     allk = np_of(allk)
     assert info["n_sources"] == len(S) and info["path"] == PATH_CODE["batched"]
     say("rmat20 sampled 1024: oracle")
@@ -555,11 +582,12 @@ def test_lattice_1024_sampled_subset(bc):
     g = bc.bc_build_csr(n, u, v)
     S = gg.uniform_sources(n, 1024, 1024)
     say("lattice1024 sampled 1024")
-    got, info = bc.bc_sampled(g, S, info=True)
+    got, flags, info = bc.bc_sampled_flags(g, S, info=True)
     assert info["n_sources"] == len(S)
     say("lattice1024 sampled 1024: oracle")
     want, ovf, st = oracle.bc(oracle.Graph(n, u, v), S)
     assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
+    check_overflow_set(flags, S, ovf, n)   # 489 of the 1,024 sources, as a set
     assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
     assert info["levels_max"] == int(st[:, 3].max())
     rel_close(np_of(got), want, what="lattice1024 sampled 1024")
@@ -635,6 +663,28 @@ def test_batch_bench_workload(bc):
         rel_close(np_of(outs[i]), want, what=f"graph {i} (scale {scales[i]})")
     for g in graphs:
         g.free()
+
+
+def test_batch_plan_dropped_with_its_graph(bc):
+    """A cached batch plan must not outlive a graph it lists: free the graph, build another of a
+    different size (its handle and output may land at the old addresses), batch again."""
+    import torch
+    n1, u1, v1 = gg.rmat(9, 8, 31)
+    n2, u2, v2 = gg.rmat(11, 8, 32)
+    w2 = oracle.bc(oracle.Graph(n2, u2, v2))[0]
+    for rep in range(3):
+        say("batch plan with a freed graph", rep)
+        g1 = bc.bc_build_csr(n1, u1, v1)
+        out = torch.empty(n2, dtype=torch.float64, device="cuda")
+        bc.bc_batch([g1], [out])
+        torch.cuda.synchronize()
+        g1.free()
+        g2 = bc.bc_build_csr(n2, u2, v2)
+        out.fill_(-1.0)
+        bc.bc_batch([g2], [out])
+        torch.cuda.synchronize()
+        rel_close(np_of(out), w2, what="batch after a freed graph")
+        g2.free()
 
 
 def test_batch_matches_oracle_and_replays(bc):
