@@ -152,6 +152,20 @@ BC_API bc_status bc_sampled(bc_graph g, const uint32_t* d_sources, int32_t k, do
 BC_API bc_status bc_sampled_flags(bc_graph g, const uint32_t* d_sources, int32_t k, double* d_bc,
                                   uint8_t* d_overflowed, const bc_tuning* t, void* stream, bc_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): bc_sampled's result from a call that allocates
+ * nothing.  It runs the one-source-per-workgroup kernel with its per-source state in one fixed
+ * 32 MiB array of device memory that the library holds on each GPU it runs on until the process
+ * ends (one state slot takes 24 n + 4 bytes, so n must be at most 1,398,079: larger graphs get
+ * BC_E_RANGE; fewer slots fit as n grows, which bounds the concurrency, not the result).  Every
+ * call on a GPU reuses that GPU's array: calls that overlap on one GPU (two streams, two
+ * threads) race and must be ordered by the caller.  The graph must be built (bc_build_csr
+ * allocates) before.  Arguments as bc_sampled; `t` may set wg_size and hub_threshold (the other
+ * fields are ignored).  Stream-ordered, no host synchronisation; bad source ids are skipped.
+ * Errors: BC_E_INVAL, BC_E_RANGE (n too large), BC_E_HIP. */
+BC_API bc_status bc_sampled_noalloc(bc_graph g, const uint32_t* d_sources, int32_t k, double* d_bc,
+                                    const bc_tuning* t, void* stream);
+
 /* One source, for inspection (section I: the BFS distances d(s,.) and shortest-path counts
  * sigma(s,.) of the forward sweep, and the dependencies delta_s(.) of the backward sweep): distances and path counts exactly as the forward sweep
  * leaves them, and the dependencies of the backward sweep.  d_dist (int32 n),

@@ -84,6 +84,7 @@ def lib():
         L.bc_approx_vertex.argtypes = [P, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), P,
                                        ctypes.c_int32, P]
+        L.bc_sampled_noalloc.argtypes = [P, P, ctypes.c_int32, P, ctypes.POINTER(bc_tuning), P]
         L.bc_stream_probe.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double)]
         L.bc_serve_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(P)]
@@ -93,7 +94,7 @@ def lib():
         for name in ["bc_build_csr", "bc_graph_info", "bc_graph_arrays", "bc_graph_order", "bc_graph_free", "bc_exact",
                      "bc_sampled", "bc_sampled_flags",
                      "bc_sssp", "bc_batch", "bc_tune", "bc_paper_strategy", "bc_approx", "bc_approx_vertex",
-                     "bc_serve_create", "bc_serve_submit", "bc_serve_poll", "bc_serve_destroy", "bc_stream_probe"]:
+                     "bc_serve_create", "bc_serve_submit", "bc_serve_poll", "bc_serve_destroy", "bc_stream_probe", "bc_sampled_noalloc"]:
             getattr(L, name).restype = ctypes.c_int32
         L.bc_last_error.restype = ctypes.c_char_p
         L.bc_version.restype = ctypes.c_char_p
@@ -271,6 +272,17 @@ def bc_sampled_flags(g: Graph, sources=None, out=None, flags=None, tuning=None, 
     if not info and srcs is not None:
         _check_keepalive(srcs, stream)
     return (out, flags, inf.as_dict()) if info else (out, flags)
+
+
+def bc_sampled_noalloc(g: Graph, sources, out, tuning=None, stream=None):
+    """bc_sampled through the entry point that allocates no device memory (its state lives in
+    the library's fixed per-device array); `out` must be given."""
+    srcs = _dev_u32(sources)
+    assert out.dtype == torch.float64 and out.numel() >= g.n and out.is_contiguous()
+    _check(lib().bc_sampled_noalloc(g.handle, P(srcs.data_ptr()) if srcs.numel() else None, srcs.numel(),
+                                    P(out.data_ptr()), ctypes.byref(tuning) if tuning else None, _stream(stream)))
+    _check_keepalive(srcs, stream)
+    return out
 
 
 def bc_paper_strategy(g: Graph, strategy: int, wg_size: int = 256, sources=None, out=None, stream=None,

@@ -473,6 +473,18 @@ bc_status bc_paper_strategy(bc_graph gh, int32_t strategy, int32_t wg_size, cons
     });
 }
 
+bc_status bc_sampled_noalloc(bc_graph gh, const uint32_t* d_sources, int32_t k, double* d_bc, const bc_tuning* t,
+                             void* stream) {
+    return guarded([&] {
+        Graph* g = as_graph(gh);
+        BC_REQUIRE(d_bc != nullptr, BC_E_INVAL, "null output array");
+        BC_REQUIRE(k >= 0, BC_E_INVAL, "k must be >= 0");
+        BC_REQUIRE(k == 0 || d_sources != nullptr, BC_E_INVAL, "null source array");
+        const Knobs kn = resolve_knobs(*g, t);
+        run_sampled_noalloc(*g, d_sources, (uint32_t)k, d_bc, kn, (hipStream_t)stream);
+    });
+}
+
 bc_status bc_stream_probe(size_t bytes, int32_t reps, double* h_copy_gbs, double* h_triad_gbs) {
     return guarded([&] { stream_probe(bytes, reps, h_copy_gbs, h_triad_gbs); });
 }

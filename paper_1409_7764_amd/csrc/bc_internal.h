@@ -262,6 +262,10 @@ uint32_t hoeffding_pivots(uint32_t n, double eps, double delta);        // n whe
 void scale_bc(double* d_bc, uint32_t n, double f, hipStream_t st);
 double read_bc_entry(const double* d_bc, uint32_t v, double* d_tmp, hipStream_t st);
 
+// ---- sampled BC with the state in the library's fixed per-device array (noalloc.hip) ---------
+void run_sampled_noalloc(Graph& g, const uint32_t* sources, uint32_t k, double* bc, const Knobs& kn, hipStream_t st);
+uint32_t noalloc_max_n();
+
 // ---- STREAM-style bandwidth probe (stream_probe.hip) -------------------------------------------
 void stream_probe(size_t bytes, int reps, double* copy_gbs, double* triad_gbs);
 
