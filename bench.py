@@ -41,14 +41,21 @@ def algorithmic_bytes(info, n):
 
     One source per workgroup (paths 0, 1, 3): 96 B per reached vertex, 16 B per examined edge,
     24 B per shortest-path DAG edge, summed over sources.
-    64-source batches (path 2): 144 B per level-list entry, 24 B per out-edge read for an
-    entry (forward + backward), 20 B per reached (vertex, source) pair (32-bit count read in
-    each sweep and cleared, psi written), 16 B per DAG (edge, source) pair (32-bit count
-    atomic, psi read), and 16 B per vertex for every level-collect pass.
+    64-source batches (path 2): 144 B per level-list entry, 12 B per out-edge read for an
+    entry in each sweep that reads it, 20 B per reached (vertex, source) pair (32-bit count
+    read in each sweep and cleared, psi written), 16 B per DAG (edge, source) pair of a pushed
+    level (32-bit count atomic, psi read), 16 B per vertex for every level-collect pass, plus
+    the pulled levels' own reads (below).
     """
     if info["path"] == 2:
-        return (144 * info["batch_entries"] + 24 * info["batch_edge_visits"] + 20 * info["reached"]
-                + 16 * info["dag_edges"] + 16 * n * info["batch_scans"])
+        # pulled forward levels: their entries' out-edges are not read forward; instead 20 B per
+        # in-edge read (CSC row 4, level record of the in-neighbour 16), 8 B per vertex per pulled
+        # level (its seen mask), and 12 B per DAG pair they find (count read 4, psi read 8)
+        pushed = info["batch_edge_visits"] - info["batch_pull_skipped"]
+        return (144 * info["batch_entries"] + 12 * info["batch_edge_visits"] + 12 * pushed
+                + 20 * info["reached"] + 16 * (info["dag_edges"] - info["batch_pull_pairs"])
+                + 12 * info["batch_pull_pairs"] + 16 * n * info["batch_scans"]
+                + 20 * info["batch_pull_edges"] + 8 * n * info["batch_pull_levels"])
     return 96 * info["reached"] + 16 * info["examined"] + 24 * info["dag_edges"]
 
 
@@ -226,6 +233,8 @@ def time_single(args, torch, bcmi, gg, name, achievable):
             "batch_entries": inf["batch_entries"], "batch_edge_visits": inf["batch_edge_visits"],
             "batch_scans": inf["batch_scans"], "batch_handoffs": inf["batch_handoffs"],
             "batch_cycles_fwd_bwd_reset": inf["batch_cycles"],
+            "batch_pull_levels": inf["batch_pull_levels"], "batch_pull_edges": inf["batch_pull_edges"],
+            "batch_pull_skipped": inf["batch_pull_skipped"], "batch_pull_pairs": inf["batch_pull_pairs"],
             "kernel_ms_all": [i["kernel_ms"] for i in infos],
         },
     }
@@ -379,40 +388,16 @@ def bench_batch(args, torch, bcmi, gg):
     return res
 
 
-def bench_serve(args, torch, bcmi, gg):
-    """Poisson stream of BC requests over a pool of resident R-MAT graphs."""
-    rng = np.random.default_rng(5)
-    pool = []
-    for i in range(64):
-        sc = int(rng.integers(8, args.serve_max_scale + 1))
-        ef = int(rng.integers(4, 17))
-        n, u, v = gg.rmat(sc, ef, 5000 + i)
-        pool.append(bcmi.bc_build_csr(n, u, v))
-    torch.cuda.synchronize()
-    N = args.serve_requests
-    gaps = rng.exponential(1.0 / args.serve_rate, size=N)
-    arrive = np.cumsum(gaps)
-    reqs = []
-    for i in range(N):
-        g = pool[int(rng.integers(0, len(pool)))]
-        if rng.random() < 0.7:
-            reqs.append((g, None, g.n))
-        else:
-            k = min(256, g.n)
-            reqs.append((g, gg.uniform_sources(g.n, k, 77 + i), k))
-    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g, _, _ in reqs]
-    srv = bcmi.bc_serve_create(200 << 30)
-    # warm-up: one request of each kind
-    for g, S, _ in reqs[:2]:
-        t = bcmi.bc_serve_submit(srv, g, S, torch.empty(g.n, dtype=torch.float64, device="cuda"))
-        while bcmi.bc_serve_poll(srv, t) is None:
-            time.sleep(0.001)
+def _serve_trace(bcmi, srv, reqs, outs, arrive, label):
+    """Submits each request at its arrival time (seconds after the start), then polls every ticket
+    to completion: (makespan seconds, infos)."""
     tickets = []
     t0 = time.perf_counter()
     for (g, S, _), out, at in zip(reqs, outs, arrive):
         while time.perf_counter() - t0 < at:
             pass
         tickets.append(bcmi.bc_serve_submit(srv, g, S, out))
+    N = len(reqs)
     infos = [None] * N
     pending = set(range(N))
     last_print = time.perf_counter()
@@ -423,22 +408,93 @@ def bench_serve(args, torch, bcmi, gg):
                 infos[i] = inf
                 pending.discard(i)
         if time.perf_counter() - last_print > 20:
-            print(f"serve: {N - len(pending)}/{N} done", file=sys.stderr, flush=True)
+            print(f"serve {label}: {N - len(pending)}/{N} done", file=sys.stderr, flush=True)
             last_print = time.perf_counter()
         time.sleep(0.0005)
-    makespan = time.perf_counter() - t0
+    return time.perf_counter() - t0, infos
+
+
+def _latency_summary(infos, makespan, reqs):
     lat = np.array([i["t_done_ms"] - i["t_submit_ms"] for i in infos])
     work = sum(k * g.m for g, _, k in reqs)
+    return {"requests": len(infos), "throughput_req_s": len(infos) / makespan, "makespan_s": makespan,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "nominal_gteps": work / makespan / 1e9}
+
+
+def bench_serve(args, torch, bcmi, gg):
+    """Poisson stream of BC requests over a pool of 64 resident R-MAT graphs (scale uniform on
+    8..serve_max_scale, i.e. log-uniform n; edge factor uniform on 4..16), 70 % exact and 30 %
+    on 256 sampled sources.  Two traces: (i) the stated arrival rate, which offers more work than
+    one GPU serves (latency is then queueing), and (ii) the same kind of requests at 70 % of the
+    capacity measured on (i).  Baselines on the same GPU, at the same accuracy (the same
+    kernels): every request of (i) as one library call after another without the server, and
+    one launch per source (timed on a sample of sources per graph, scaled to each request)."""
+    rng = np.random.default_rng(5)
+    pool = []
+    for i in range(64):
+        sc = int(rng.integers(8, args.serve_max_scale + 1))
+        ef = int(rng.integers(4, 17))
+        n, u, v = gg.rmat(sc, ef, 5000 + i)
+        pool.append(bcmi.bc_build_csr(n, u, v))
+    torch.cuda.synchronize()
+    N = args.serve_requests
+    arrive = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=N))
+    reqs = []
+    for i in range(N):
+        g = pool[int(rng.integers(0, len(pool)))]
+        if rng.random() < 0.7:
+            reqs.append((g, None, g.n))
+        else:
+            k = min(256, g.n)
+            reqs.append((g, gg.uniform_sources(g.n, k, 77 + i), k))
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g, _, _ in reqs]
+    srv = bcmi.bc_serve_create(200 << 30)
+    for g, S, _ in reqs[:2]:   # warm-up: one request of each kind
+        t = bcmi.bc_serve_submit(srv, g, S, torch.empty(g.n, dtype=torch.float64, device="cuda"))
+        while bcmi.bc_serve_poll(srv, t) is None:
+            time.sleep(0.001)
+    makespan, infos = _serve_trace(bcmi, srv, reqs, outs, arrive, "stated rate")
+    first = _latency_summary(infos, makespan, reqs)
+    first["offered_rate_req_s"] = args.serve_rate
+    capacity = first["throughput_req_s"]
+    # (ii) rate-scaled: the first requests again, arriving at 70 % of the measured capacity
+    N2 = min(N, args.serve_scaled_requests)
+    rate2 = 0.7 * capacity
+    arrive2 = np.cumsum(np.random.default_rng(55).exponential(1.0 / rate2, size=N2))
+    makespan2, infos2 = _serve_trace(bcmi, srv, reqs[:N2], outs[:N2], arrive2, "scaled rate")
+    second = _latency_summary(infos2, makespan2, reqs[:N2])
+    second["offered_rate_req_s"] = rate2
     bcmi.bc_serve_destroy(srv)
-    res = {"metric": "served BC requests: throughput and p50/p99 latency", "value": N / makespan,
+    res = {"metric": "served BC requests: throughput and p50/p99 latency", "value": first["throughput_req_s"],
            "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 2, "ms_per_step": makespan * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64+f64",
            "data": "synthetic",
            "config": {"workload": f"served-poisson{args.serve_rate:g}-rmat8to{args.serve_max_scale}-ef4to16",
                       "requests": N, "exact_fraction": 0.7, "sampled_k": 256, "graph_pool": 64},
-           "extra": {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                     "mean_ms": float(lat.mean()), "nominal_gteps": work / makespan / 1e9,
-                     "offered_rate_req_s": args.serve_rate}}
+           "extra": {"stated_rate": first, "scaled_rate": second}}
+    if not args.skip_compare:
+        # one library call per request, back to back (no server, no continuous batching)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (g, S, _), out in zip(reqs, outs):
+            if S is None:
+                bcmi.bc_exact(g, out=out)
+            else:
+                bcmi.bc_sampled(g, S, out=out)
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t0
+        # one launch per source: per graph, a sample of single-source launches
+        per_src = {}
+        for g, _, _ in reqs:
+            if id(g) not in per_src:
+                per_src[id(g)] = one_source_per_launch_ms(bcmi, torch, g, np.arange(g.n), 16)
+        plain_s = sum(k * per_src[id(g)] for g, _, k in reqs) / 1e3
+        res["extra"]["one_call_per_request"] = {"makespan_s": seq, "throughput_req_s": N / seq,
+                                                "speedup_of_server": seq / makespan}
+        res["extra"]["one_launch_per_source_estimated"] = {"makespan_s": plain_s, "throughput_req_s": N / plain_s,
+                                                           "speedup_of_server": plain_s / makespan,
+                                                           "sample": "16 single-source launches per graph"}
     for g in pool:
         g.free()
     return res
@@ -453,7 +509,9 @@ def main():
                     choices=["rmat16", "rmat20", "lattice", "batch", "serve", "paper"])
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="mean arrivals per second")
-    ap.add_argument("--serve-max-scale", type=int, default=14)
+    ap.add_argument("--serve-max-scale", type=int, default=18)
+    ap.add_argument("--serve-scaled-requests", type=int, default=128,
+                    help="requests of the rate-scaled trace (70 %% of the measured capacity)")
     ap.add_argument("--tune", action="store_true", help="autotune launch knobs first (untimed)")
     ap.add_argument("--strategy", default="auto", choices=["auto", "batched", "per-source"])
     ap.add_argument("--knob", action="append", default=[], help="launch knob override, e.g. batch_wg_size=512")
@@ -462,7 +520,7 @@ def main():
     ap.add_argument("--no-stream-probe", action="store_true",
                     help="skip the STREAM-style bandwidth probe (roofline.achievable is then null)")
     ap.add_argument("--skip-compare", action="store_true",
-                    help="batch workload: skip the one-launch-per-graph / per-source comparisons")
+                    help="batch and serve workloads: skip the comparisons with plain launches")
     ap.add_argument("--plain-baseline", action="store_true",
                     help="also time the one-launch-per-source path on a sample of sources")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the CPU oracle sample")

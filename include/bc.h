@@ -75,6 +75,11 @@ typedef struct {
                                    2 = one source per workgroup with each level held in LDS
                                        (switched off: BC_E_INVAL) */
     int32_t batch_wg_size;      /* workgroup size of the batched kernel: 256, 512, 1024 */
+    int32_t batch_pull;         /* batched kernel, direction of the forward sweep: a level is
+                                   built from the unreached vertices' in-edges (pulled) instead
+                                   of its entries' out-edges when (in-edges of vertices some
+                                   source has not reached) * 16 < (out-edges of the level's
+                                   entries) * batch_pull; < 0 = always pushed (0 = automatic: 32) */
 } bc_tuning;
 
 typedef struct {
@@ -100,6 +105,12 @@ typedef struct {
                                        LDS tables) */
     uint64_t batch_cycles[3];       /* path 2: workgroup clock cycles summed over workgroups, in the
                                        forward sweep, the backward sweep, and state reset */
+    uint64_t batch_pull_edges;      /* path 2: in-edges read by pulled forward levels */
+    uint64_t batch_pull_levels;     /* path 2: forward levels pulled, summed over batches (each reads
+                                       every vertex's masks once) */
+    uint64_t batch_pull_skipped;    /* path 2: out-edges of the entries of pulled levels, which the
+                                       forward sweep did not read */
+    uint64_t batch_pull_pairs;      /* path 2: DAG (edge, source) pairs found by pulled levels */
 } bc_info;
 
 /* Build a graph handle from a pair list (section II-D: edge list A[i]=u, B[i]=v).

@@ -33,7 +33,7 @@ class bc_tuning(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("wgs_per_source", ctypes.c_int32),
                 ("sources_per_launch", ctypes.c_int32), ("hub_threshold", ctypes.c_int32),
                 ("lds_max_n", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("batched", ctypes.c_int32),
-                ("batch_wg_size", ctypes.c_int32)]
+                ("batch_wg_size", ctypes.c_int32), ("batch_pull", ctypes.c_int32)]
 
 
 class bc_info(ctypes.Structure):
@@ -44,7 +44,9 @@ class bc_info(ctypes.Structure):
                 ("dag_edges", ctypes.c_uint64), ("batch_entries", ctypes.c_uint64),
                 ("batch_edge_visits", ctypes.c_uint64), ("batch_scans", ctypes.c_uint64),
                 ("batch_handoffs", ctypes.c_uint64),
-                ("batch_cycles", ctypes.c_uint64 * 3)]
+                ("batch_cycles", ctypes.c_uint64 * 3), ("batch_pull_edges", ctypes.c_uint64),
+                ("batch_pull_levels", ctypes.c_uint64), ("batch_pull_skipped", ctypes.c_uint64),
+                ("batch_pull_pairs", ctypes.c_uint64)]
 
     def as_dict(self):
         out = {k: getattr(self, k) for k, _ in self._fields_}

@@ -146,6 +146,10 @@ static void fill_info(Graph& g, hipStream_t st, int path, double ms, uint32_t ex
     out.batch_scans = cs.scans;
     out.batch_handoffs = cs.handoffs;
     for (int i = 0; i < 3; ++i) out.batch_cycles[i] = cs.cycles[i];
+    out.batch_pull_edges = cs.pull_edges;
+    out.batch_pull_levels = cs.pull_levels;
+    out.batch_pull_skipped = cs.pull_skip;
+    out.batch_pull_pairs = cs.pull_pairs;
     *info = out;
 }
 
@@ -504,6 +508,7 @@ bc_status bc_tune(bc_graph gh, bc_tuning* out) {
         r.use_graph = k.use_graph ? 1 : -1;
         r.batched = k.batched;
         r.batch_wg_size = k.batch_wg;
+        r.batch_pull = k.batch_pull > 0 ? k.batch_pull : -1;
         *out = r;
     });
 }

@@ -69,6 +69,10 @@ struct CallStats {
     uint64_t edge_visits;    // batched path: out-edges read per entry (once per sweep)
     uint64_t scans;          // batched path: level-collect passes over all vertices
     uint64_t cycles[3];      // batched path: workgroup clock cycles in forward, backward, reset
+    uint64_t pull_edges;     // batched path: in-edges read by pulled levels
+    uint64_t pull_levels;    // batched path: levels pulled (summed over batches)
+    uint64_t pull_skip;      // batched path: out-edges of the entries of pulled levels (not pushed)
+    uint64_t pull_pairs;     // batched path: DAG (edge, source) pairs found by pulled levels
 };
 
 // Launch knobs after defaults / tuning are applied.
@@ -82,6 +86,8 @@ struct Knobs {
     int batched = 0;             // 1: 64-source batches, -1: one source per workgroup, 2: one source per
                                  // workgroup with its levels in LDS, 0: auto
     int batch_wg = 1024;         // workgroup size of the batched kernel
+    int batch_pull = 32;         // batched path: pull a level when (in-edges of unreached vertices) * 16 <
+                                 // (out-edges of the level) * batch_pull; <= 0 = never
 };
 
 // Graph handle (the opaque bc_graph).
@@ -237,7 +243,8 @@ size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels);
 // device count, capacity, list holds kernel ids, stream)
 using RetryLaunch = void (*)(void*, const uint32_t*, const uint32_t*, uint32_t, bool, hipStream_t);
 void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
-                     int wg, int team_knob, int slots_cap, hipStream_t st, RetryLaunch retry_launch, void* retry_ctx);
+                     int wg, int team_knob, int slots_cap, int pull16, hipStream_t st, RetryLaunch retry_launch,
+                     void* retry_ctx);
 
 // ---- one source per workgroup, levels in LDS (narrow.hip) ---------------------------------
 struct NarrowPool;

@@ -1132,8 +1132,8 @@ int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     z.grid = 0;
     enqueue_plan(z, st, (uint32_t)g.n);
     RetryCtx rc{&g, &gs, k, ra.bc, ra.ovf_flags};
-    run_msb_enqueue(*gs.msb, g, ra.sources, ra.num_items, ra.bc, g.stats, k.batch_wg, k.team, k.teams, st,
-                    retry_launch, &rc);
+    run_msb_enqueue(*gs.msb, g, ra.sources, ra.num_items, ra.bc, g.stats, k.batch_wg, k.team, k.teams, k.batch_pull,
+                    st, retry_launch, &rc);
     return 2;
 }
 

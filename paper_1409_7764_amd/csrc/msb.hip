@@ -25,6 +25,14 @@
 //   a time, so a pair of units costs two dependent memory round trips.  The level-(d+1) list
 //   is then collected by one coalesced pass over nxt (entries in vertex order), which also
 //   folds the masks into seen.
+// pulled levels (direction-optimising forward): when the vertices that some source of the batch
+//   has not reached have fewer in-edges than the level's entries have out-edges, level d + 1 is
+//   built from the other side.  Every vertex w with unreached lanes u(w) reads its in-edges
+//   (CSC) and the level-d lanes cur[x] of each in-neighbour x; lane s sums sigma_s(x) over the
+//   in-neighbours whose lanes hold s, and w stores its own row and next-mask: no count atomics,
+//   and only the in-edges of unreached vertices are read (late levels, where most out-edges of
+//   a wide frontier lead back into reached vertices).  The same cap on the summed counts flags
+//   a lane before any sum can wrap.  The backward sweep does not depend on the direction.
 // backward, level d, entry (v, f): succ = f & nxt[w] are the sources with w one level down;
 //   lane s sums psi_s(w), then delta_s(v) = sigma_s(v) * sum, psi_s(v) is stored, and sum
 //   over s != v of delta_s(v) is added to BC[v].  Each (v, s) has one
@@ -53,7 +61,8 @@ struct alignas(128) TeamCtl {
     uint32_t abort;          // a barrier wait ran out: every member leaves
     uint32_t sdeg[2];        // out-degree sum of a level (double-buffered by level parity)
     uint64_t ovf;            // sources whose counts carried out of 64 bits
-    uint32_t pad[16];
+    uint32_t pin[2];         // in-edges of vertices some source has not reached yet, by level parity
+    uint32_t pad[14];
 };
 
 struct MsbArgs {
@@ -87,6 +96,13 @@ struct MsbArgs {
     uint32_t sig_cap;            // largest count c with c * (largest in-degree) < 2^32
     uint64_t* bnx;               // [teams][n]: backward sweep, level-(d+1) masks; zero between batches
     uint64_t bnx_stride;
+    const uint32_t* csc_ptr;     // pulled levels: in-edges of each vertex
+    const uint32_t* csc_row;
+    ulonglong2* cur;             // [teams][n]: {lanes on level d, d + 1} of the vertices listed on level d;
+                                 // zero between batches
+    uint64_t cur_stride;
+    uint32_t pull16;             // a level is pulled when (in-edges of vertices with unreached lanes) * 16 <
+                                 // (out-edges of the level's entries) * pull16; 0 = never
 };
 
 namespace {
@@ -157,7 +173,8 @@ struct MsbLds {
     int32_t eh[WG];         // accumulator row of a split entry, -1 otherwise
     uint32_t hub_ent[WG];   // accumulator row -> chunk entry
     double hl[WG / 8][64];  // the first accumulator rows (LDS atomics: no wait on memory)
-    unsigned long long ws[WG / 64][4];   // per wavefront: reached pairs, examined, entries, visits
+    unsigned long long ws[WG / 64][6];   // per wavefront: reached pairs, examined, entries, visits, pulled
+                                         // in-edges, DAG (edge, source) pairs of pulled levels
     uint32_t nhub;
     uint32_t chunk;
     uint32_t ucnt;          // next unit of the chunk to claim
@@ -252,9 +269,13 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total,
 // Collects a level: every vertex whose next-mask is non-zero becomes an entry (w, mask) of
 // the team's level list; the mask is folded into seen and the next-mask cleared.  Each
 // thread takes kScanUnroll vertices per pass (loads first), each wavefront one list append.
+// With pulls enabled (`cur` non-null) it also publishes each entry's lanes and level in `cur`
+// and sums, into `pin`, the in-degrees of the vertices that some lane of the batch has still not
+// reached: what pulling the next level would read.
 constexpr int kScanUnroll = 8;
-__device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, const Masks mk, uint32_t* lv, uint64_t* lm, uint32_t first, uint32_t stride,
-                                                  uint32_t n) {
+__device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, const Masks mk, uint32_t* lv,
+                                                  uint64_t* lm, uint32_t first, uint32_t stride, uint32_t n,
+                                                  ulonglong2* cur, uint64_t lanes, uint32_t tag, uint32_t& pin) {
     const unsigned lane = lane_id();
     const uint64_t below = (1ull << lane) - 1ull;
     uint32_t sdeg = 0;
@@ -262,10 +283,23 @@ __device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, 
         uint64_t m[kScanUnroll];
         uint64_t bal[kScanUnroll];
         uint32_t cnt = 0;
+        if (cur) {
 #pragma unroll
-        for (int j = 0; j < kScanUnroll; ++j) {
-            const uint32_t w = b0 + j * stride;
-            m[j] = w < n ? mk.nxt(w) : 0ull;
+            for (int j = 0; j < kScanUnroll; ++j) {
+                const uint32_t w = b0 + j * stride;
+                m[j] = 0ull;
+                if (w < n) {
+                    const ulonglong2 q = mk.both(w);
+                    m[j] = q.y;
+                    if (lanes & ~(q.x | q.y)) pin += a.csc_ptr[w + 1] - a.csc_ptr[w];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kScanUnroll; ++j) {
+                const uint32_t w = b0 + j * stride;
+                m[j] = w < n ? mk.nxt(w) : 0ull;
+            }
         }
 #pragma unroll
         for (int j = 0; j < kScanUnroll; ++j) {
@@ -286,6 +320,7 @@ __device__ __forceinline__ uint32_t collect_level(const MsbArgs& a, TeamCtl* c, 
                 __hip_atomic_fetch_or((unsigned long long*)&mk.seen(w), (unsigned long long)m[j], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
                 mk.nxt(w) = 0ull;
+                if (cur) cur[w] = make_ulonglong2(m[j], (unsigned long long)tag);
                 sdeg += a.row_ptr[w + 1] - a.row_ptr[w];
             }
             base += (uint32_t)__builtin_popcountll(bal[j]);
@@ -350,6 +385,68 @@ __device__ __forceinline__ void fwd_units(const MsbArgs& a, MsbLds<WG>& L, const
     if (lane == 0 && risk) atomicOr((unsigned long long*)&L.ovf, (unsigned long long)risk);
     rows_add(sig, wA, dagA, svA);
     rows_add(sig, wB, dagB, svB);
+}
+
+// One unit of a pulled level: in-edges [e0, e1) of vertex w, whose lanes `un` are unreached.
+// Lane per in-edge first (in-neighbour x and its level-d lanes), then lane per source: the
+// counts of the in-neighbours holding the lane are summed, kPullLoads rows in flight.  A vertex
+// with more in-edges than one unit (`split`) adds its partial sums and next-mask with atomics;
+// otherwise it is the only writer of its row and next-mask.  Counts this lane's in-edge read and
+// its DAG (edge, source) pairs into `read` and `pairs`.
+constexpr int kPullLoads = 16;
+template <int WG>
+__device__ __forceinline__ void pull_unit(const MsbArgs& a, MsbLds<WG>& L, const Masks mk, uint32_t* sig,
+                                              const ulonglong2* cur, uint32_t w, uint64_t un, uint32_t e0,
+                                              uint32_t e1, bool split, uint64_t tag, uint32_t& read,
+                                              uint32_t& pairs) {
+    const unsigned lane = lane_id();
+    const uint32_t e = e0 + lane;
+    const bool ok = e < e1;
+    const uint32_t x = a.csc_row[ok ? e : e1 - 1];
+    const ulonglong2 c = cur[x];
+    const uint64_t lx = (ok && c.y == tag) ? (c.x & un) : 0ull;   // lanes with x on level d: (x, w) on their DAG
+    uint64_t rem = __ballot(lx != 0ull);
+    uint64_t nx = 0;
+    uint32_t acc = 0;
+    bool risk = false;
+    while (rem) {
+        uint32_t y[kPullLoads];
+#pragma unroll
+        for (int q = 0; q < kPullLoads; ++q) {
+            y[q] = 0u;
+            if (rem) {
+                const int k = __builtin_ctzll(rem);
+                rem &= rem - 1ull;
+                const uint32_t xk = readlane_u32(x, k);
+                const uint64_t mk_ = readlane_u64(lx, k);
+                nx |= mk_;
+                if ((mk_ >> lane) & 1ull) y[q] = sig[(size_t)xk * 64 + lane];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPullLoads; ++q) {
+            risk |= y[q] > a.sig_cap;
+            acc += y[q];
+        }
+    }
+    if (nx) {
+        const bool mine = (nx >> lane) & 1ull;
+        if (!split) {
+            if (lane == 0) mk.nxt(w) = nx;
+            if (mine) sig[(size_t)w * 64 + lane] = acc;
+        } else {
+            if (lane == 0)
+                __hip_atomic_fetch_or((unsigned long long*)&mk.nxt(w), (unsigned long long)nx, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            if (mine && acc)
+                __hip_atomic_fetch_add(&sig[(size_t)w * 64 + lane], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // a lane that summed a count beyond the cap is handed on, as in the pushed levels
+    const uint64_t flag = __ballot(risk);
+    if (lane == 0 && flag) atomicOr((unsigned long long*)&L.ovf, (unsigned long long)flag);
+    read += ok ? 1u : 0u;
+    pairs += (uint32_t)__builtin_popcountll(lx);
 }
 
 // finishes list entry idx = (v, f) of level d with the summed successor psi in `acc`;
@@ -432,6 +529,9 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     uint32_t* sig = a.sig + (size_t)team * a.sig_stride;
     double* psi = a.psi + (size_t)team * a.psi_stride;
     uint64_t* bnx = a.bnx + (size_t)team * a.bnx_stride;
+    ulonglong2* cur = a.pull16 ? a.cur + (size_t)team * a.cur_stride : nullptr;
+    uint32_t pull_levels = 0;   // leader's thread 0: levels pulled, and the out-edges they did not push
+    uint64_t pull_skip = 0;
     double* hacc = a.hacc + (size_t)blockIdx.x * a.hub_rows * 64;
     double* bcp = a.bcp + (size_t)team * a.cap;
     constexpr uint32_t HL = WG / 8;   // accumulator rows in LDS
@@ -449,7 +549,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     uint64_t cyc[3] = {0, 0, 0};   // thread 0: clock cycles in forward, backward, reset
 
     if (lane == 0)
-        for (int q = 0; q < 4; ++q) L.ws[wave][q] = 0ull;
+        for (int q = 0; q < 6; ++q) L.ws[wave][q] = 0ull;
     if (tid == 0) {
         L.nhub = 0;
         L.ovf = 0;
@@ -461,6 +561,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             ctl->cc = 0;
             ctl->ovf = 0;
             ctl->sdeg[0] = ctl->sdeg[1] = 0;
+            ctl->pin[0] = ctl->pin[1] = 0;
         }
         if (!team_sync(L, ctl, W, a.stats)) break;
         const uint32_t b = ld_team(&ctl->batch);
@@ -487,11 +588,18 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             if (leader && tid == 0) {
                 ctl->cc = 0;                       // chunk counter of this level's expansion
                 ctl->sdeg[(d + 1) & 1] = 0;        // filled by the next level's scan
+                ctl->pin[(d + 1) & 1] = 0;
             }
             // level d: the vertices some source reached in the previous expansion
-            uint32_t sdeg = collect_level(a, ctl, mk, lv, lm, member * WG + tid, gthreads, (uint32_t)n);
+            uint32_t pin = 0;
+            uint32_t sdeg = collect_level(a, ctl, mk, lv, lm, member * WG + tid, gthreads, (uint32_t)n, cur, lanes,
+                                          d + 1, pin);
             sdeg = wave_sum_u32(sdeg);
             if (lane == 0 && sdeg) atomicAdd(&ctl->sdeg[d & 1], sdeg);
+            if (cur) {
+                pin = wave_sum_u32(pin);
+                if (lane == 0 && pin) atomicAdd(&ctl->pin[d & 1], pin);
+            }
             if (!team_sync(L, ctl, W, a.stats)) {
                 aborted = true;
                 break;
@@ -503,12 +611,59 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             }
             if (hi == lo) break;   // level d is empty: the sweep is over (levels 0..d-1)
             const uint64_t room = (uint64_t)a.cap - hi;
-            if (d + 2 > a.max_levels || room < min<uint64_t>(n, ld_team(&ctl->sdeg[d & 1]))) {
+            const uint32_t lsdeg = ld_team(&ctl->sdeg[d & 1]);
+            if (d + 2 > a.max_levels || room < min<uint64_t>(n, lsdeg)) {
                 stopped = true;
                 d += 1;
                 break;
             }
-            for (;;) {
+            // the same values in every member: the whole team takes the same direction
+            const bool pull = cur && (uint64_t)ld_team(&ctl->pin[d & 1]) * 16u < (uint64_t)lsdeg * a.pull16;
+            if (pull && leader && tid == 0) {
+                ++pull_levels;
+                pull_skip += lsdeg;
+            }
+            for (;;) {   // pulled level: chunks of WG vertices, units of <= 64 in-edges
+                if (!pull) break;
+                const uint32_t ch = claim_chunk(L, ctl);
+                const uint32_t c0 = ch * WG;
+                if (c0 >= (uint32_t)n) break;
+                const uint32_t w = c0 + tid;
+                uint32_t beg = 0, deg = 0;
+                uint64_t un = 0;
+                if (w < (uint32_t)n) {
+                    un = lanes & ~mk.seen(w);
+                    if (un) {
+                        beg = a.csc_ptr[w];
+                        deg = a.csc_ptr[w + 1] - beg;
+                    }
+                }
+                uint32_t units;
+                const uint32_t off = block_excl_scan<WG>((deg + 63) / 64, units, L.wsum);
+                L.off[tid] = off;
+                fill_owners<WG>(L, off, (deg + 63) / 64);
+                L.ev[tid] = w;
+                L.em[tid] = un;
+                L.eb[tid] = beg;
+                L.ed[tid] = deg;
+                __syncthreads();
+                uint32_t read = 0, pairs = 0;
+                for (;;) {
+                    const uint32_t u = claim_units(L, 1u);
+                    if (u >= units) break;
+                    const uint32_t j = owner_of<WG>(L, u);
+                    const uint32_t e0 = L.eb[j] + (u - L.off[j]) * 64;
+                    const uint32_t e1 = min(L.eb[j] + L.ed[j], e0 + 64);
+                    pull_unit<WG>(a, L, mk, sig, cur, L.ev[j], L.em[j], e0, e1, L.ed[j] > 64, d + 1, read, pairs);
+                }
+                read = wave_sum_u32(read);
+                pairs = wave_sum_u32(pairs);
+                if (lane == 0 && read) atomicAdd(&L.ws[wave][4], (unsigned long long)read);
+                if (lane == 0 && pairs) atomicAdd(&L.ws[wave][5], (unsigned long long)pairs);
+                __syncthreads();
+            }
+            for (;;) {   // pushed level
+                if (pull) break;
                 const uint32_t ch = claim_chunk(L, ctl);
                 const uint32_t c0 = lo + ch * CH;
                 if (c0 >= hi) break;
@@ -702,6 +857,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             const uint64_t m = lm[i];
             mk.clear(v);
             bnx[v] = 0ull;
+            if (cur) cur[v] = make_ulonglong2(0ull, 0ull);
             if (!stopped && (m & ~ovf)) {
                 const double c = bcp[i];
                 if (c != 0.0) unsafeAtomicAdd(&a.bc[a.iperm ? a.iperm[v] : v], c);
@@ -745,11 +901,16 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
         if (g_w) atomicAdd((unsigned long long*)&a.stats->dag_edges, (unsigned long long)g_w);
         if (n_w) atomicAdd((unsigned long long*)&a.stats->entries, n_w);
         if (v_w) atomicAdd((unsigned long long*)&a.stats->edge_visits, v_w);
+        const unsigned long long p_w = L.ws[wave][4], q_w = L.ws[wave][5];
+        if (p_w) atomicAdd((unsigned long long*)&a.stats->pull_edges, p_w);
+        if (q_w) atomicAdd((unsigned long long*)&a.stats->pull_pairs, q_w);
     }
     if (tid == 0) {
         if (n_done) atomicAdd(&a.stats->n_done, n_done);
         if (scans) atomicAdd((unsigned long long*)&a.stats->scans, (unsigned long long)scans);
         if (levels_max) atomicMax(&a.stats->levels_max, levels_max);
+        if (pull_levels) atomicAdd((unsigned long long*)&a.stats->pull_levels, (unsigned long long)pull_levels);
+        if (pull_skip) atomicAdd((unsigned long long*)&a.stats->pull_skip, (unsigned long long)pull_skip);
         for (int i = 0; i < 3; ++i)
             if (cyc[i]) atomicAdd((unsigned long long*)&a.stats->cycles[i], (unsigned long long)cyc[i]);
     }
@@ -878,6 +1039,8 @@ struct MsbPool {
     uint64_t mask_stride = 0, sig_stride = 0, psi_stride = 0, bnx_stride = 0;
     TeamCtl* ctl = nullptr;
     uint64_t *masks = nullptr, *lst_m = nullptr, *bnx = nullptr;
+    ulonglong2* cur = nullptr;
+    uint64_t cur_stride = 0;
     uint32_t* sig = nullptr;
     double *psi = nullptr, *bcp = nullptr;
     double* hacc = nullptr;
@@ -890,12 +1053,12 @@ struct MsbPool {
 };
 
 size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels) {
-    return sizeof(TeamCtl) + (size_t)n * (16 + 8 + 256 + 512) + 4 * kStaggerWords * 8 + (size_t)cap * 20 +
+    return sizeof(TeamCtl) + (size_t)n * (16 + 8 + 16 + 256 + 512) + 5 * kStaggerWords * 8 + (size_t)cap * 20 +
            4 * ((size_t)max_levels + 2);
 }
 
 void msb_pool_free(MsbPool& p) {
-    for (void* q : {(void*)p.ctl, (void*)p.masks, (void*)p.bnx, (void*)p.sig, (void*)p.psi, (void*)p.bcp, (void*)p.lst_m, (void*)p.hacc,
+    for (void* q : {(void*)p.ctl, (void*)p.masks, (void*)p.bnx, (void*)p.cur, (void*)p.sig, (void*)p.psi, (void*)p.bcp, (void*)p.lst_m, (void*)p.hacc,
                     (void*)p.lst_v, (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small, (void*)p.bhist})
         if (q) (void)hipFree(q);
     p = MsbPool{};
@@ -933,9 +1096,11 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     p.sig_stride = (uint64_t)n * 64 + 2 * kStaggerWords;
     p.psi_stride = (uint64_t)n * 64 + kStaggerWords;
     p.bnx_stride = (uint64_t)n + kStaggerWords / 8;
+    p.cur_stride = (uint64_t)n + kStaggerWords / 16;
     BC_HIP_TRY(hipMalloc((void**)&p.ctl, (size_t)teams * sizeof(TeamCtl)));
     BC_HIP_TRY(hipMalloc((void**)&p.masks, (size_t)teams * p.mask_stride * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.bnx, (size_t)teams * p.bnx_stride * 8));
+    BC_HIP_TRY(hipMalloc((void**)&p.cur, (size_t)teams * p.cur_stride * 16));
     BC_HIP_TRY(hipMalloc((void**)&p.sig, (size_t)teams * p.sig_stride * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.psi, (size_t)teams * p.psi_stride * 8));
     BC_HIP_TRY(hipMalloc((void**)&p.hacc, (size_t)wgs * hub_rows * 512));
@@ -953,6 +1118,9 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     const size_t bwords = (size_t)teams * p.bnx_stride;
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<size_t>((bwords + 255) / 256, 65536)), dim3(256), 0, st,
                        p.bnx, bwords);
+    const size_t cwords = (size_t)teams * p.cur_stride * 2;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<size_t>((cwords + 255) / 256, 65536)), dim3(256), 0, st,
+                       (uint64_t*)p.cur, cwords);
     const size_t swords = (size_t)teams * p.sig_stride / 2;   // counts, as 64-bit words
     const unsigned g2 = (unsigned)std::min<size_t>((swords + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u64, dim3(g2), dim3(256), 0, st, (uint64_t*)p.sig, swords);
@@ -965,7 +1133,8 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
 // Enqueues the batched path: source plan, batched sweeps, then the per-source kernel on the
 // sources handed back.  `retry_launch` enqueues that per-source launch over (list, count).
 void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc, CallStats* stats,
-                     int wg, int team_knob, int slots_cap, hipStream_t st, RetryLaunch retry_launch, void* retry_ctx) {
+                     int wg, int team_knob, int slots_cap, int pull16, hipStream_t st, RetryLaunch retry_launch,
+                     void* retry_ctx) {
     const DevInfo& di = dev_info(g.device);
     wg = msb_norm_wg(wg);
     const uint32_t n = (uint32_t)g.n;
@@ -1051,6 +1220,13 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     a.sig_cap = g.max_in_degree ? (uint32_t)(0xffffffffull / g.max_in_degree) : 0xffffffffu;
     a.bnx = p.bnx;
     a.bnx_stride = p.bnx_stride;
+    if (pull16 > 0) {
+        a.csc_ptr = g.csc_ptr;
+        a.csc_row = g.csc_row;
+        a.cur = p.cur;
+        a.cur_stride = p.cur_stride;
+        a.pull16 = (uint32_t)pull16;
+    }
     void* args[] = {&a};
     // members of a team wait for each other at level boundaries: a cooperative launch
     // guarantees that every workgroup of the grid is resident at once

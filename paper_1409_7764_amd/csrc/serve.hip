@@ -297,8 +297,8 @@ struct Server {
             hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, st, bs, 2u);
             BC_HIP_TRY(hipGetLastError());
             HandOff h{this, &r, bs + 1, tk.h_rdesc + i, tk.d_rdesc + i};
-            run_msb_enqueue(*msb, *r.g, b.sources, b.take, r.d_bc, bs, knobs.batch_wg, 0, kServeTeams, st,
-                            serve_hand_off, &h);
+            run_msb_enqueue(*msb, *r.g, b.sources, b.take, r.d_bc, bs, knobs.batch_wg, 0, kServeTeams, knobs.batch_pull,
+                            st, serve_hand_off, &h);
             hipLaunchKernelGGL(k_fold_counters, dim3(1), dim3(1), 0, st, bs, bs + 1, r.d_counters, tk.d_flag);
             BC_HIP_TRY(hipGetLastError());
         }

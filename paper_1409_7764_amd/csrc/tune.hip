@@ -35,6 +35,7 @@ Knobs default_knobs(const Graph& g) {
     k.use_graph = true;
     k.batched = 0;
     k.batch_wg = 1024;
+    k.batch_pull = 32;
     return k;
 }
 
@@ -64,9 +65,9 @@ void load_cache_locked() {
     char key[256];
     Knobs k;
     int ug = 0;
-    // one entry per line: key wg hub lds_max_n batched batch_wg teams use_graph team
-    while (std::fscanf(f, "%255s %d %d %d %d %d %d %d %d", key, &k.wg_size, &k.hub, &k.lds_max_n, &k.batched,
-                       &k.batch_wg, &k.teams, &ug, &k.team) == 9) {
+    // one entry per line: key wg hub lds_max_n batched batch_wg teams use_graph team batch_pull
+    while (std::fscanf(f, "%255s %d %d %d %d %d %d %d %d %d", key, &k.wg_size, &k.hub, &k.lds_max_n, &k.batched,
+                       &k.batch_wg, &k.teams, &ug, &k.team, &k.batch_pull) == 10) {
         k.use_graph = ug != 0;
         g_cache[key] = k;
     }
@@ -80,8 +81,8 @@ void save_cache_locked() {
     if (!f) return;
     for (const auto& kv : g_cache) {
         const Knobs& k = kv.second;
-        std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", kv.first.c_str(), k.wg_size, k.hub, k.lds_max_n,
-                     k.batched, k.batch_wg, k.teams, k.use_graph ? 1 : 0, k.team);
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d\n", kv.first.c_str(), k.wg_size, k.hub, k.lds_max_n,
+                     k.batched, k.batch_wg, k.teams, k.use_graph ? 1 : 0, k.team, k.batch_pull);
     }
     std::fclose(f);
 }
@@ -122,6 +123,7 @@ Knobs resolve_knobs(Graph& g, const bc_tuning* t) {
         BC_REQUIRE(t->batched >= -1 && t->batched <= 2, BC_E_INVAL, "batched must be -1, 0, 1 or 2");
         k.batched = t->batched;
     }
+    if (t->batch_pull) k.batch_pull = t->batch_pull;
     if (t->batch_wg_size) {
         BC_REQUIRE(t->batch_wg_size == 256 || t->batch_wg_size == 512 || t->batch_wg_size == 1024, BC_E_INVAL,
                    "batch_wg_size must be 256, 512 or 1024");

@@ -229,6 +229,58 @@ def test_batched_flagged_counts_shallow_graph(bc):
     g.free()
 
 
+PULL = {"push": -1, "auto": 0, "always": 1 << 24}
+
+
+def _pull_case(case):
+    if case == "rmat10":
+        n, u, v = gg.rmat(10, 8, 10)
+        return n, u, v, None
+    if case == "rmat13_sampled":
+        n, u, v = gg.rmat(13, 16, 3)
+        S = gg.uniform_sources(n, 700, 4)
+        return n, u, v, np.concatenate([S, S[:40], np.zeros(3, np.uint32)])
+    if case == "lattice64":          # deep: batches run out of room and hand sources back
+        n, u, v = gg.grid_random_orientation(64, 64, 1)
+        return n, u, v, None
+    if case == "grid_dag35":         # counts past 2^64 from the corner
+        n, u, v = gg.grid_dag(35, 35)
+        return n, u, v, None
+    if case == "diamond_forest":     # counts past the 32-bit cap: flagged lanes
+        n, u, v = gg.wide_diamond_forest(40, 16, 8)
+        return n, u, v, None
+    n, u, v = gg.barabasi_albert(3000, 6, 2)   # symmetric: every vertex reached from every source
+    return n, u, v, None
+
+
+@pytest.mark.parametrize("mode", sorted(PULL))
+@pytest.mark.parametrize("case", ["rmat10", "rmat13_sampled", "lattice64", "grid_dag35", "diamond_forest", "ba3000"])
+def test_batched_forward_directions(bc, case, mode):
+    """The batched kernel with every forward level pushed (out-edges of the level's entries),
+    pulled where the unreached vertices have fewer in-edges (the default), and pulled whenever
+    possible: BC, the overflow set, the work counters and the deepest level all equal the
+    oracle's in each mode."""
+    n, u, v, S = _pull_case(case)
+    want, ovf, st = oracle.bc(oracle.Graph(n, u, v), S)
+    g = bc.bc_build_csr(n, u, v)
+    say("forward direction", case, mode)
+    tun = bc.tuning(lds_max_n=-1, batched=1, batch_pull=PULL[mode])
+    got, flags, info = bc.bc_sampled_flags(g, S, tuning=tun, info=True)
+    assert info["path"] == PATH_CODE["batched"]
+    assert info["n_sources"] == (n if S is None else len(S))
+    assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+    assert info["levels_max"] == int(st[:, 3].max())
+    assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
+    check_overflow_set(flags, S, ovf, n)
+    rel_close(np_of(got), want, what=f"{case} {mode}")
+    assert info["batch_pull_pairs"] <= info["dag_edges"]
+    if mode == "push":
+        assert info["batch_pull_levels"] == info["batch_pull_edges"] == info["batch_pull_pairs"] == 0
+    if mode == "always" and case != "lattice64":
+        assert info["batch_pull_levels"] > 0 and info["batch_pull_edges"] > 0 and info["batch_pull_pairs"] > 0
+    g.free()
+
+
 def test_relabelled_graph_every_path(bc):
     """Graphs from 16,384 vertices run on an internally renumbered copy; every output must
     still come back in the caller's vertex ids."""

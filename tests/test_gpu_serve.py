@@ -35,9 +35,10 @@ def wait(bc, srv, ticket, timeout=120.0):
 
 def msb_team_bytes(n):
     """Device state of one batched team: control block, masks 16n + counts 256n + psi 512n,
-    bnx 8n, staggers, level lists (8n + 64 entries of 20 B) and 1026 level offsets."""
+    bnx 8n, level masks of pulled levels 16n, staggers, level lists (8n + 64 entries of 20 B)
+    and 1026 level offsets."""
     cap = 8 * n + 64
-    return 128 + n * (16 + 8 + 256 + 512) + 4 * 37 * 512 * 8 + cap * 20 + 4 * (1024 + 2)
+    return 128 + n * (16 + 8 + 16 + 256 + 512) + 5 * 37 * 512 * 8 + cap * 20 + 4 * (1024 + 2)
 
 
 def footprint(n, m, k, path):
