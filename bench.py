@@ -348,15 +348,41 @@ def bench_batch(args, torch, bcmi, gg):
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
     outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in graphs]
-    for _ in range(args.warmup):
-        bcmi.bc_batch(graphs, outs, info=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for _ in range(args.steps):
-        infos.append(bcmi.bc_batch(graphs, outs, info=True)[1])
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    def timed():
+        for _ in range(args.warmup):
+            bcmi.bc_batch(graphs, outs, info=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for _ in range(args.steps):
+            infos.append(bcmi.bc_batch(graphs, outs, info=True)[1])
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps, infos
+
+    ms, infos = timed()
+    tuned = None
+    if args.tune:
+        # the autotuner on the largest graph of each size class (floor(log2 n), round(log2 m/n));
+        # bc_batch then resolves every graph's knobs from its class's entry
+        default_ms, default_out = ms, [o.clone() for o in outs]
+        reps = {}
+        for g in graphs:
+            key = (int(np.floor(np.log2(g.n))), int(round(np.log2(max(1.0, g.m / g.n)))))
+            if key not in reps or g.n * g.m > reps[key].n * reps[key].m:
+                reps[key] = g
+        knobs = {f"n2^{k[0]} d2^{k[1]}": bcmi.bc_tune(g) for k, g in sorted(reps.items())}
+        ms, infos = timed()
+        worst = 0.0
+        for a, b in zip(outs, default_out):
+            a, b = a.cpu().numpy(), b.cpu().numpy()
+            nz = b != 0
+            assert np.all(a[~nz] == 0), "tuned batch changed a structural zero"
+            if nz.any():
+                worst = max(worst, float(np.max(np.abs(a[nz] - b[nz]) / np.abs(b[nz]))))
+        assert worst <= 1e-9, f"tuned batch differs from the default one by {worst}"
+        tuned = {"default_ms": default_ms, "tuned_ms": ms, "speedup": default_ms / ms,
+                 "max_rel_diff_vs_default": worst, "knobs_by_class": knobs}
     nominal = sum(g.n * g.m for g in graphs)
     per_graph_ms = per_source_ms = float("nan")
     if not args.skip_compare:
@@ -378,7 +404,7 @@ def bench_batch(args, torch, bcmi, gg):
            "dtype": "u64+f64", "data": "synthetic",
            "config": {"workload": "batch4096-rmat6to12-ef8", "graphs": 4096,
                       "sum_n": int(sum(g.n for g in graphs)), "sum_m": int(sum(g.m for g in graphs))},
-           "extra": {"build_csr_ms_total": build_ms, "kernel_ms": infos[-1][0]["kernel_ms"],
+           "extra": {"build_csr_ms_total": build_ms, "kernel_ms": infos[-1][0]["kernel_ms"], "autotune": tuned,
                      "one_exact_launch_per_graph_ms": per_graph_ms,
                      "one_launch_per_source_ms_estimated": per_source_ms,
                      "speedup_vs_launch_per_graph": per_graph_ms / ms,

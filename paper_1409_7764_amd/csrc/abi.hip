@@ -319,7 +319,7 @@ bc_status bc_sssp(bc_graph gh, uint32_t s, int32_t* d_dist, uint64_t* d_sigma_u6
 }  // extern "C"
 
 namespace bcmi {
-void run_batch(const bc_graph* gs, int num, double* const* bcs, const Knobs& k, hipStream_t st, bc_info* infos,
+void run_batch(const bc_graph* gs, int num, double* const* bcs, const bc_tuning* t, hipStream_t st, bc_info* infos,
                double* kernel_ms);
 Knobs tune_graph(Graph& g);
 }  // namespace bcmi
@@ -339,8 +339,7 @@ bc_status bc_batch(const bc_graph* gs, int32_t num_graphs, double* const* d_bcs,
             BC_REQUIRE(d_bcs[i] != nullptr, BC_E_INVAL, "null output array");
             BC_REQUIRE(g->device == dev, BC_E_INVAL, "graph lives on another device");
         }
-        const Knobs kn = resolve_knobs(*as_graph(gs[0]), t);
-        run_batch(gs, num_graphs, d_bcs, kn, (hipStream_t)stream, infos, nullptr);
+        run_batch(gs, num_graphs, d_bcs, t, (hipStream_t)stream, infos, nullptr);
     });
 }
 

@@ -1174,26 +1174,42 @@ void read_stats(Graph& g, hipStream_t st, CallStats* out) {
 
 
 // ---------------------------------------------------------------------------------------
-// batch of independent graphs: one work list over every (graph, source) pair, largest graphs
-// first; graphs that fit the LDS-resident path share one persistent launch, larger ones a
-// second one over global-memory slots.  The whole sequence (zeroing, searches) is captured
-// once into a hipGraph and replayed while the same graphs and outputs come back.
+// batch of independent graphs: one work list over every (graph, source) pair.  Each graph's
+// launch knobs are resolved on their own (the autotuner's entry for the graph's size class,
+// else the defaults, then the caller's overrides); graphs that share a state home (LDS-resident
+// or global slots), workgroup size, hub threshold and grid cap share one persistent launch, and
+// inside a launch the graphs run largest work first.  The whole sequence (zeroing, searches) is
+// captured once into a hipGraph and replayed while the same graphs, outputs and knobs come back.
 // ---------------------------------------------------------------------------------------
+struct LaunchKey {
+    int lds = 0;      // 1: LDS-resident state
+    int wg = 256;
+    int hub = 0;
+    int teams = 0;    // grid cap (sources per launch), 0 = fill the device
+    bool operator==(const LaunchKey& o) const { return lds == o.lds && wg == o.wg && hub == o.hub && teams == o.teams; }
+    bool operator<(const LaunchKey& o) const {
+        if (lds != o.lds) return lds > o.lds;
+        if (wg != o.wg) return wg < o.wg;
+        if (hub != o.hub) return hub < o.hub;
+        return teams < o.teams;
+    }
+};
+
 struct BatchPlan {
     int device = 0;
     std::vector<const Graph*> graphs;
     std::vector<uint64_t> uids;       // the graphs' identities (addresses can be reused)
     std::vector<double*> outs;
-    Knobs knobs;
+    std::vector<LaunchKey> keys;      // per graph: the launch it runs in
+    bool use_graph = true;
     WorkDesc* d_descs = nullptr;      // [ndesc]
     uint32_t* d_counters = nullptr;   // [ndesc][4]
-    CallStats* d_stats = nullptr;     // [2] one per launch class
+    CallStats* d_stats = nullptr;     // one per launch
     SlotPool pool;
     std::vector<int> order;           // desc index -> graph index
     std::vector<int> path;            // desc index -> 1 LDS-resident, 0 global slots
-    LaunchPlan lp[2];
-    uint32_t maxn[2] = {0, 0};
-    int nclass = 0;
+    std::vector<LaunchPlan> lp;
+    std::vector<uint32_t> maxn;
     hipGraph_t hg = nullptr;
     hipGraphExec_t exec = nullptr;
 
@@ -1205,14 +1221,12 @@ struct BatchPlan {
         if (d_stats) (void)hipFree(d_stats);
         pool_free(pool);
     }
-    bool same(const bc_graph* gs, int num, double* const* bcs, const Knobs& k, int dev) const {
-        if (dev != device || num != (int)graphs.size()) return false;
-        if (k.wg_size != knobs.wg_size || k.hub != knobs.hub || k.lds_max_n != knobs.lds_max_n ||
-            k.teams != knobs.teams || k.use_graph != knobs.use_graph)
-            return false;
+    bool same(const bc_graph* gs, int num, double* const* bcs, const std::vector<LaunchKey>& k, bool ug,
+              int dev) const {
+        if (dev != device || num != (int)graphs.size() || ug != use_graph) return false;
         for (int i = 0; i < num; ++i) {
             const Graph* g = (const Graph*)gs[i];
-            if (g != graphs[i] || g->uid != uids[i] || bcs[i] != outs[i]) return false;
+            if (g != graphs[i] || g->uid != uids[i] || bcs[i] != outs[i] || !(k[i] == keys[i])) return false;
         }
         return true;
     }
@@ -1227,7 +1241,7 @@ static std::mutex g_batch_mu;
 static BatchPlan* g_batch_plan = nullptr;
 
 static void enqueue_batch(BatchPlan& bp, hipStream_t st) {
-    for (int c = 0; c < bp.nclass; ++c) enqueue_plan(bp.lp[c], st, bp.maxn[c]);
+    for (size_t c = 0; c < bp.lp.size(); ++c) enqueue_plan(bp.lp[c], st, bp.maxn[c]);
 }
 
 // Called when a graph handle is freed: a plan that lists it is dropped before its arrays go.
@@ -1239,21 +1253,41 @@ void batch_forget_graph(const Graph* g) {
     }
 }
 
-static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* bcs, const Knobs& k, int dev,
-                                   hipStream_t st) {
+// The launch each graph of a batch runs in, from its own resolved knobs.
+static std::vector<LaunchKey> batch_keys(const bc_graph* gs, int num, const bc_tuning* t, int dev, bool* use_graph) {
+    std::vector<LaunchKey> keys(num);
+    *use_graph = true;
+    for (int i = 0; i < num; ++i) {
+        Graph& g = *(Graph*)gs[i];
+        const Knobs k = resolve_knobs(g, t);
+        keys[i].lds = lds_fits(k, (uint32_t)g.n, dev) ? 1 : 0;
+        keys[i].wg = norm_wg(k.wg_size);
+        keys[i].hub = k.hub;
+        keys[i].teams = k.teams;
+        if (i == 0) *use_graph = k.use_graph;
+    }
+    return keys;
+}
+
+static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* bcs, const std::vector<LaunchKey>& keys,
+                                   bool use_graph, int dev, hipStream_t st) {
     BatchPlan* bp = new BatchPlan();
     try {
         bp->device = dev;
-        bp->knobs = k;
+        bp->keys = keys;
+        bp->use_graph = use_graph;
         for (int i = 0; i < num; ++i) {
             bp->graphs.push_back((const Graph*)gs[i]);
             bp->uids.push_back(((const Graph*)gs[i])->uid);
             bp->outs.push_back(bcs[i]);
         }
-        // class 0: LDS-resident graphs, class 1: the rest; each class largest work first
-        auto fits_lds = [&](const Graph* g) { return lds_fits(k, (uint32_t)g->n, dev); };
-        std::vector<int> cls[2];
-        for (int i = 0; i < num; ++i) cls[fits_lds(bp->graphs[i]) ? 0 : 1].push_back(i);
+        // launches: graphs grouped by key, each group largest work first
+        std::vector<LaunchKey> uniq(keys.begin(), keys.end());
+        std::sort(uniq.begin(), uniq.end());
+        uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+        std::vector<std::vector<int>> cls(uniq.size());
+        for (int i = 0; i < num; ++i)
+            cls[std::lower_bound(uniq.begin(), uniq.end(), keys[i]) - uniq.begin()].push_back(i);
         for (auto& v : cls)
             std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
                 const double wa = (double)bp->graphs[a]->n * (bp->graphs[a]->m + 1);
@@ -1263,10 +1297,12 @@ static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* b
         std::vector<WorkDesc> h(num);
         BC_HIP_TRY(hipMalloc((void**)&bp->d_descs, sizeof(WorkDesc) * std::max(num, 1)));
         BC_HIP_TRY(hipMalloc((void**)&bp->d_counters, sizeof(uint32_t) * 4 * std::max(num, 1)));
-        BC_HIP_TRY(hipMalloc((void**)&bp->d_stats, sizeof(CallStats) * 2));
+        BC_HIP_TRY(hipMalloc((void**)&bp->d_stats, sizeof(CallStats) * std::max<size_t>(uniq.size(), 1)));
         int pos = 0;
-        for (int c = 0; c < 2; ++c) {
-            if (cls[c].empty()) continue;
+        uint32_t pool_n = 0;
+        long pool_slots = 0;
+        std::vector<int> firsts;
+        for (size_t c = 0; c < uniq.size(); ++c) {
             const int first = pos;
             uint32_t items = 0, maxn = 0;
             for (int gi : cls[c]) {
@@ -1289,30 +1325,36 @@ static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* b
                 bp->order.push_back(gi);
                 ++pos;
             }
-            const size_t mark = bp->path.size();
-            Knobs kc = k;
-            if (c == 1) kc.lds_max_n = -1;
+            Knobs kc;
+            kc.wg_size = uniq[c].wg;
+            kc.hub = uniq[c].hub;
+            kc.teams = uniq[c].teams;
+            kc.lds_max_n = uniq[c].lds ? (int)std::max<uint32_t>(maxn, 1) : -1;
             LaunchPlan lp = make_plan(kc, maxn, items, dev);
             if (!lp.lds_path) {
-                pool_ensure(bp->pool, maxn, (int)lp.grid, st);
+                pool_n = std::max(pool_n, maxn);
+                pool_slots = std::max<long>(pool_slots, lp.grid);
+            }
+            lp.args.descs = bp->d_descs + first;
+            lp.args.ndesc = (uint32_t)(pos - first);
+            lp.args.total_items = items;
+            lp.args.stats = bp->d_stats + c;
+            bp->path.resize(pos, lp.lds_path ? 1 : 0);
+            bp->lp.push_back(lp);
+            bp->maxn.push_back(maxn);
+        }
+        // one slot pool serves every global-slot launch (they run one after another)
+        if (pool_slots > 0) pool_ensure(bp->pool, pool_n, (int)pool_slots, st);
+        for (LaunchPlan& lp : bp->lp)
+            if (!lp.lds_path) {
                 lp.args.rec = bp->pool.rec;
                 lp.args.queue = bp->pool.queue;
                 lp.args.lvl = bp->pool.lvl;
                 lp.args.slot_n = bp->pool.slot_n;
             }
-            lp.args.descs = bp->d_descs + first;
-            lp.args.ndesc = (uint32_t)(pos - first);
-            lp.args.total_items = items;
-            lp.args.stats = bp->d_stats + bp->nclass;
-            bp->path.resize(pos, lp.lds_path ? 1 : 0);
-            (void)mark;
-            bp->lp[bp->nclass] = lp;
-            bp->maxn[bp->nclass] = maxn;
-            bp->nclass++;
-        }
         BC_HIP_TRY(hipMemcpyAsync(bp->d_descs, h.data(), sizeof(WorkDesc) * num, hipMemcpyHostToDevice, st));
         BC_HIP_TRY(hipStreamSynchronize(st));
-        if (k.use_graph) {
+        if (use_graph) {
             hipStream_t cs;
             BC_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
             hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -1339,15 +1381,17 @@ static BatchPlan* build_batch_plan(const bc_graph* gs, int num, double* const* b
     return bp;
 }
 
-void run_batch(const bc_graph* gs, int num, double* const* bcs, const Knobs& k, hipStream_t st, bc_info* infos,
+void run_batch(const bc_graph* gs, int num, double* const* bcs, const bc_tuning* t, hipStream_t st, bc_info* infos,
                double* kernel_ms) {
     int dev = 0;
     BC_HIP_TRY(hipGetDevice(&dev));
+    bool use_graph = true;
+    const std::vector<LaunchKey> keys = batch_keys(gs, num, t, dev, &use_graph);
     std::lock_guard<std::mutex> lk(g_batch_mu);
-    if (!g_batch_plan || !g_batch_plan->same(gs, num, bcs, k, dev)) {
+    if (!g_batch_plan || !g_batch_plan->same(gs, num, bcs, keys, use_graph, dev)) {
         delete g_batch_plan;
         g_batch_plan = nullptr;
-        g_batch_plan = build_batch_plan(gs, num, bcs, k, dev, st);
+        g_batch_plan = build_batch_plan(gs, num, bcs, keys, use_graph, dev, st);
     }
     BatchPlan& bp = *g_batch_plan;
     hipEvent_t e0 = nullptr, e1 = nullptr;

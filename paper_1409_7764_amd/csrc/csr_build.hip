@@ -254,20 +254,29 @@ __global__ void k_perm_from_sorted(const uint64_t* keys, uint32_t n, int vbits, 
     }
 }
 
-// relabelled edge keys, one thread per row
+// relabelled edge keys, one wavefront per row (its lanes stride the row: coalesced, and a
+// long row does not hold up a single thread)
 __global__ void k_relabel_keys(const uint32_t* row_ptr, const uint32_t* col, uint32_t n, const uint32_t* perm,
                                int vbits, uint64_t* keys) {
-    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const uint32_t lane = lane_id();
+    const uint32_t waves = gridDim.x * (blockDim.x / 64);
+    for (uint32_t u = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; u < n; u += waves) {
         const uint64_t hi = (uint64_t)perm[u] << vbits;
-        for (uint32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) keys[e] = hi | perm[col[e]];
+        const uint32_t e1 = row_ptr[u + 1];
+        for (uint32_t e = row_ptr[u] + lane; e < e1; e += 64) keys[e] = hi | perm[col[e]];
     }
 }
 
-__global__ void k_csr_from_sorted(const uint64_t* keys, uint64_t m, int vbits, uint32_t* col, uint32_t* deg) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = keys[i];
-        col[i] = (uint32_t)(k & ((1ull << vbits) - 1));
-        atomicAdd(&deg[(uint32_t)(k >> vbits)], 1u);
+__global__ void k_csr_from_sorted(const uint64_t* keys, uint64_t m, int vbits, uint32_t* col) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x)
+        col[i] = (uint32_t)(keys[i] & ((1ull << vbits) - 1));
+}
+
+// out-degree of relabelled vertex i: the original vertex's, read from its row offsets
+__global__ void k_relabel_degrees(const uint32_t* row_ptr, const uint32_t* iperm, uint32_t n, uint32_t* deg) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t v = iperm[i];
+        deg[i] = row_ptr[v + 1] - row_ptr[v];
     }
 }
 
@@ -552,7 +561,9 @@ void build_csr_device(int32_t n, int64_t m_in, const uint32_t* d_src, const uint
         uint64_t* rs = radix_sort(keys, tmp, m, 2 * vbits, st);
         BC_HIP_TRY(hipMemsetAsync(g.prow, 0, sizeof(uint32_t) * (n + 1), st));
         hipLaunchKernelGGL(k_csr_from_sorted, dim3(std::min<unsigned>(grid_for(m, 256), 8192)), dim3(256), 0, st, rs,
-                           (uint64_t)m, vbits, g.pcol, g.prow);
+                           (uint64_t)m, vbits, g.pcol);
+        BC_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_relabel_degrees, dim3(gn), dim3(256), 0, st, g.row_ptr, g.iperm, (uint32_t)n, g.prow);
         BC_HIP_TRY(hipGetLastError());
         scan_u32(g.prow, g.prow, (uint64_t)n + 1, st);
         BC_HIP_TRY(hipFreeAsync(dk, st));

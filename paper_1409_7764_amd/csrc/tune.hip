@@ -1,6 +1,7 @@
 // Launch knobs: built-in defaults, the autotuner and its cache, explicit caller overrides.
 //
-// The tuner times candidate configurations (state home, workgroup size, hub threshold,
+// The tuner times candidate configurations (state home, workgroup size, hub threshold, sources
+// per launch; for the batched kernel its workgroup size, workgroups per batch and pull threshold;
 // batched vs one source per workgroup) on an evenly strided sample of the graph's sources
 // and keeps the fastest per graph class: (device, floor(log2 n), round(log2(m/n))).  Results
 // live in memory for the process and, when BCMI_TUNE_CACHE names a file, in that JSON file.
@@ -137,20 +138,36 @@ Knobs tune_graph(Graph& g) {
     const Knobs base = default_knobs(g);
     std::vector<Knobs> cands;
     const bool small = lds_fits(base, (uint32_t)g.n, g.device);
+    const int cus = dev_info(g.device).cus;
     if (small) {
+        // workgroup size, hub threshold, and sources per launch (the persistent grid: every
+        // resident workgroup, or one per compute unit)
         for (int wg : {64, 128, 256, 512})
-            for (int hub : {64, 128}) {
+            for (int hub : {64, 128})
+                for (int teams : {0, cus}) {
+                    if (teams && wg < 256) continue;
+                    Knobs k = base;
+                    k.wg_size = wg;
+                    k.hub = hub;
+                    k.teams = teams;
+                    k.batched = -1;
+                    cands.push_back(k);
+                }
+    } else {
+        // batched: workgroup size, workgroups per batch (0 = from the batch count), and the
+        // forward's pull threshold
+        for (int bwg : {512, 1024})
+            for (int team : {0, 2, 8}) {
                 Knobs k = base;
-                k.wg_size = wg;
-                k.hub = hub;
-                k.batched = -1;
+                k.batched = 1;
+                k.batch_wg = bwg;
+                k.team = team;
                 cands.push_back(k);
             }
-    } else {
-        for (int bwg : {512, 1024}) {
+        for (int pull : {16, 64}) {
             Knobs k = base;
             k.batched = 1;
-            k.batch_wg = bwg;
+            k.batch_pull = pull;
             cands.push_back(k);
         }
         for (int wg : {256, 512})

@@ -198,6 +198,34 @@ def test_autotune_keeps_results(bc):
     g2.free()
 
 
+def test_batch_resolves_tuned_knobs_per_class(bc):
+    """bc_batch resolves each graph's knobs from the tuner's entry for its size class: after
+    tuning one graph of two classes, a batch mixing them (and an untuned class) still equals
+    the oracle, and equals the batch run before tuning."""
+    import torch
+    specs = [(9, 8, 300 + i) for i in range(6)] + [(11, 8, 310 + i) for i in range(4)] + [(13, 8, 320), (13, 8, 321)]
+    graphs, wants = [], []
+    for sc, ef, seed in specs:
+        n, u, v = gg.rmat(sc, ef, seed)
+        graphs.append(bc.bc_build_csr(n, u, v))
+        wants.append(oracle.bc(oracle.Graph(n, u, v))[0])
+    before = bc.bc_batch(graphs)
+    torch.cuda.synchronize()
+    for o, w in zip(before, wants):
+        rel_close(o.cpu().numpy(), w, what="batch before tuning")
+    bc.bc_tune(graphs[0])     # class of the scale-9 graphs (LDS-resident)
+    bc.bc_tune(graphs[-1])    # class of the scale-13 graphs (global slots or batched candidates)
+    for rep in range(2):      # a new plan, then its replay
+        after, infos = bc.bc_batch(graphs, info=True)
+        torch.cuda.synchronize()
+        for i, (o, b, w) in enumerate(zip(after, before, wants)):
+            rel_close(o.cpu().numpy(), w, what=f"batch after tuning, graph {i}")
+            rel_close(o.cpu().numpy(), b.cpu().numpy(), 1e-11, what=f"tuned vs default, graph {i}")
+            assert infos[i]["n_sources"] == graphs[i].n
+    for g in graphs:
+        g.free()
+
+
 @pytest.mark.slow
 def test_serve_bench_workload(bc):
     """The benchmark's served stream, replayed: 256 requests over a pool of 64 resident
