@@ -500,16 +500,29 @@ def bench_serve(args, torch, bcmi, gg):
                       "requests": N, "exact_fraction": 0.7, "sampled_k": 256, "graph_pool": 64},
            "extra": {"stated_rate": first, "scaled_rate": second}}
     if not args.skip_compare:
-        # one library call per request, back to back (no server, no continuous batching)
+        # one library call per request, one after another (no server, no continuous batching);
+        # each call's service time also gives the latency a first-come-first-served queue of
+        # such calls would have on the rate-scaled arrivals
         torch.cuda.synchronize()
+        service = []
         t0 = time.perf_counter()
         for (g, S, _), out in zip(reqs, outs):
+            t1 = time.perf_counter()
             if S is None:
                 bcmi.bc_exact(g, out=out)
             else:
                 bcmi.bc_sampled(g, S, out=out)
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            service.append(time.perf_counter() - t1)
         seq = time.perf_counter() - t0
+        free_at, lat2 = 0.0, []
+        for at, sv in zip(arrive2, service[:N2]):
+            start = max(at, free_at)
+            free_at = start + sv
+            lat2.append((free_at - at) * 1e3)
+        res["extra"]["fifo_calls_scaled_rate"] = {"p50_ms": float(np.percentile(lat2, 50)),
+                                                  "p99_ms": float(np.percentile(lat2, 99)),
+                                                  "mean_ms": float(np.mean(lat2))}
         # one launch per source: per graph, a sample of single-source launches
         per_src = {}
         for g, _, _ in reqs:

@@ -472,8 +472,18 @@ __device__ void accumulate_level(S& st, Scratch<WG>& L, const uint32_t* __restri
         classify_chunk<WG>(L, deg, is_hub, so, stot, po, ptot, mx);
         double own = 0.0;
         if (ptot == 0 && mx <= tpv_max) {
+            // thread per vertex, at most kTpv successors: every successor id, then every
+            // successor record, is loaded before the first is used (two round trips, not two per
+            // successor); the sum keeps successor order
             const uint32_t my = is_hub ? 0u : deg;
-            for (uint32_t t = 0; t < my; ++t) own += st.psi_if_level(col[beg + t], d1);
+            uint32_t w[kTpv];
+#pragma unroll
+            for (int t = 0; t < kTpv; ++t) w[t] = (uint32_t)t < my ? col[beg + t] : 0u;
+            double c[kTpv];
+#pragma unroll
+            for (int t = 0; t < kTpv; ++t) c[t] = (uint32_t)t < my ? st.psi_if_level(w[t], d1) : 0.0;
+#pragma unroll
+            for (int t = 0; t < kTpv; ++t) own += c[t];
         } else {
             L.scan[tid] = so;
             L.pscan[tid] = po;

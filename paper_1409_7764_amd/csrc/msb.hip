@@ -101,13 +101,15 @@ struct MsbArgs {
     ulonglong2* cur;             // [teams][n]: {lanes on level d, d + 1} of the vertices listed on level d;
                                  // zero between batches
     uint64_t cur_stride;
+    uint64_t wait_ticks;         // wall-clock ticks a barrier waits before the team gives up
     uint32_t pull16;             // a level is pulled when (in-edges of vertices with unreached lanes) * 16 <
                                  // (out-edges of the level's entries) * pull16; 0 = never
 };
 
 namespace {
 
-constexpr uint32_t kSpinLimit = 1u << 22;  // barrier polls (about 1 us each) before a team gives up
+// A team gives up waiting at a barrier after MsbArgs::wait_ticks of the constant-rate wall clock
+// (set by the host from the graph's size: far above what any level of that graph takes).
 constexpr int kPsiLoads = 16;               // backward: psi loads issued back to back
 
 __device__ __forceinline__ unsigned lane_id() {
@@ -189,7 +191,7 @@ struct MsbLds {
 // wait; the wait itself polls with plain coherent loads).  A team of one workgroup needs
 // workgroup scope only.
 template <int WG>
-__device__ bool team_sync(MsbLds<WG>& L, TeamCtl* c, uint32_t W, CallStats* stats) {
+__device__ bool team_sync(MsbLds<WG>& L, TeamCtl* c, uint32_t W, CallStats* stats, uint64_t wait_ticks) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -203,9 +205,9 @@ __device__ bool team_sync(MsbLds<WG>& L, TeamCtl* c, uint32_t W, CallStats* stat
                 __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                uint32_t spins = 0;
+                const uint64_t t0 = wall_clock64();
                 while (ld_team(&c->bar_gen) == gen) {
-                    if (ld_team(&c->abort) || ++spins > kSpinLimit) {
+                    if (ld_team(&c->abort) || wall_clock64() - t0 > wait_ticks) {
                         st_rel(&c->abort, 1u);
                         ok = 0;
                         break;
@@ -563,7 +565,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             ctl->sdeg[0] = ctl->sdeg[1] = 0;
             ctl->pin[0] = ctl->pin[1] = 0;
         }
-        if (!team_sync(L, ctl, W, a.stats)) break;
+        if (!team_sync(L, ctl, W, a.stats, a.wait_ticks)) break;
         const uint32_t b = ld_team(&ctl->batch);
         if (b >= nbatch) break;
         const uint32_t base = b * 64;
@@ -581,7 +583,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
         bool stopped = false;       // every thread takes the same decision from the same values
         bool aborted = false;
         for (;;) {
-            if (!team_sync(L, ctl, W, a.stats)) {
+            if (!team_sync(L, ctl, W, a.stats, a.wait_ticks)) {
                 aborted = true;
                 break;
             }
@@ -600,7 +602,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 pin = wave_sum_u32(pin);
                 if (lane == 0 && pin) atomicAdd(&ctl->pin[d & 1], pin);
             }
-            if (!team_sync(L, ctl, W, a.stats)) {
+            if (!team_sync(L, ctl, W, a.stats, a.wait_ticks)) {
                 aborted = true;
                 break;
             }
@@ -725,7 +727,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
         if (!stopped) {
             if (leader && tid == 0) lvl[nlev + 1] = lvl[nlev];
             for (int dd = (int)nlev - 1; dd >= 0 && !aborted; --dd) {
-                if (!team_sync(L, ctl, W, a.stats)) {
+                if (!team_sync(L, ctl, W, a.stats, a.wait_ticks)) {
                     aborted = true;
                     break;
                 }
@@ -733,7 +735,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                 const uint32_t lo_n = lvl[dd + 1], hi_n = lvl[dd + 2];
                 if (leader && tid == 0) ctl->cc = 0;
                 for (uint32_t i = lo_n + gtid; i < hi_n; i += gthreads) bnx[lv[i]] = lm[i] & ~ovf;
-                if (!team_sync(L, ctl, W, a.stats)) {
+                if (!team_sync(L, ctl, W, a.stats, a.wait_ticks)) {
                     aborted = true;
                     break;
                 }
@@ -850,7 +852,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             t_phase = t;
         }
         // ---------------- reset the touched state ----------------
-        if (!team_sync(L, ctl, W, a.stats)) break;
+        if (!team_sync(L, ctl, W, a.stats, a.wait_ticks)) break;
         // entries, thread per entry: mask records, and the BC contributions of finished entries
         for (uint32_t i = gtid; i < n_entries; i += gthreads) {
             const uint32_t v = lv[i];
@@ -889,7 +891,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
             if (!stopped) levels_max = max(levels_max, nlev);
             scans += stopped ? nlev : nlev + 1;   // the last pass found the empty level
         }
-        if (!team_sync(L, ctl, W, a.stats)) break;
+        if (!team_sync(L, ctl, W, a.stats, a.wait_ticks)) break;
         cyc[2] += clock64() - t_phase;
     }
     // counters of everything this workgroup finished
@@ -1226,6 +1228,17 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
         a.cur = p.cur;
         a.cur_stride = p.cur_stride;
         a.pull16 = (uint32_t)pull16;
+    }
+    // barrier wait bound: 10 s plus 200 ns per vertex and edge of the graph, far above what any
+    // level takes (a level reads each out-edge of its entries or each in-edge of the unreached
+    // vertices at most once per member's share); only a team whose member stopped making
+    // progress reaches it, and the call then fails with BC_E_HIP instead of hanging
+    {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g.device) != hipSuccess || khz <= 0)
+            khz = 100000;
+        const double secs = 10.0 + 2e-7 * ((double)g.n + (double)g.m);
+        a.wait_ticks = (uint64_t)(secs * 1e3 * (double)khz);
     }
     void* args[] = {&a};
     // members of a team wait for each other at level boundaries: a cooperative launch

@@ -228,18 +228,22 @@ def test_batch_resolves_tuned_knobs_per_class(bc):
 
 @pytest.mark.slow
 def test_serve_bench_workload(bc):
-    """The benchmark's served stream, replayed: 256 requests over a pool of 64 resident
-    R-MAT graphs (scales 8 to 14, edge factors 4 to 16), 70 % exact and 30 % on 256 sampled
-    sources, submitted at the same Poisson arrival times (2,000 per second).  Every request's
-    result equals the oracle's."""
+    """The benchmark's served stream, replayed: 256 requests over a pool of 64 resident R-MAT
+    graphs (scales 8 to 18, log-uniform n; edge factors 4 to 16), 70 % exact and 30 % on 256
+    sampled sources, submitted at the same Poisson arrival times (2,000 per second).  Every
+    sampled request, and every exact request on a graph of scale <= 14, equals the oracle; an
+    exact request on a larger graph (10^10 to 10^12 edge visits, beyond the oracle's reach here)
+    equals the same graph's bc_exact run alone, outside the server, which the oracle pins on
+    other graphs."""
     import torch
     rng = np.random.default_rng(5)
-    pool, coo = [], []
+    pool, coo, scales = [], [], []
     for i in range(64):
-        sc = int(rng.integers(8, 15))
+        sc = int(rng.integers(8, 19))
         ef = int(rng.integers(4, 17))
         n, u, v = gg.rmat(sc, ef, 5000 + i)
         coo.append((n, u, v))
+        scales.append(sc)
         pool.append(bc.bc_build_csr(n, u, v))
     arrive = np.cumsum(rng.exponential(1.0 / 2000.0, size=256))
     reqs = []
@@ -259,19 +263,23 @@ def test_serve_bench_workload(bc):
             pass
         tickets.append(bc.bc_serve_submit(srv, pool[gi], S, out))
     print("served stream: submitted", flush=True)
-    infos = [wait(bc, srv, t, timeout=300.0) for t in tickets]
+    infos = [wait(bc, srv, t, timeout=600.0) for t in tickets]
     bc.bc_serve_destroy(srv)
-    print("served stream: done; oracle", flush=True)
+    print("served stream: done; checking", flush=True)
     exact = {}
     for i, ((gi, S), out, inf) in enumerate(zip(reqs, outs, infos)):
         n, u, v = coo[gi]
         if S is None:
             if gi not in exact:
-                exact[gi] = oracle.bc(oracle.Graph(n, u, v))[0]
+                if scales[gi] <= 14:
+                    exact[gi] = oracle.bc(oracle.Graph(n, u, v))[0]
+                else:
+                    exact[gi] = bc.bc_exact(pool[gi]).cpu().numpy()
             want = exact[gi]
         else:
             want = oracle.bc(oracle.Graph(n, u, v), S)[0]
         assert inf["n_sources"] == (n if S is None else len(S))
-        rel_close(out.cpu().numpy(), want, what=f"request {i} (graph {gi}, {'exact' if S is None else 'sampled'})")
+        rel_close(out.cpu().numpy(), want,
+                  what=f"request {i} (graph {gi}, scale {scales[gi]}, {'exact' if S is None else 'sampled'})")
     for g in pool:
         g.free()
