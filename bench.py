@@ -36,10 +36,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+KERNEL_OF_PATH = {0: "k_bc_global", 1: "k_bc_lds", 2: "k_msb", 7: "k_bc_deep"}
+PATH_NAME = {0: "global", 1: "lds", 2: "batched", 7: "deep"}
+
+
 def algorithmic_bytes(info, n):
     """Bytes the launch's design must move, from its exact work counters.
 
-    One source per workgroup (paths 0, 1, 3): 96 B per reached vertex, 16 B per examined edge,
+    One source per workgroup (paths 0, 1, 7): 96 B per reached vertex, 16 B per examined edge,
     24 B per shortest-path DAG edge, summed over sources.
     64-source batches (path 2): 144 B per level-list entry, 12 B per out-edge read for an
     entry in each sweep that reads it, 20 B per reached (vertex, source) pair (32-bit count
@@ -217,7 +221,7 @@ def time_single(args, torch, bcmi, gg, name, achievable):
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(cfg["workload"], 1),
             "achievable": achievable, "frac_of_achievable": achieved / achievable if achievable else None,
-            "kernel": ["k_bc_global", "k_bc_lds", "k_msb", "k_bc_narrow"][inf["path"]],
+            "kernel": KERNEL_OF_PATH[inf["path"]],
             "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": nbytes,
             "per_source_convention_gbs": per_source}
     res = {
@@ -229,7 +233,7 @@ def time_single(args, torch, bcmi, gg, name, achievable):
             "sources": k, "reached": inf["reached"], "examined": inf["examined"],
             "dag_edges": inf["dag_edges"], "levels_max": inf["levels_max"],
             "sigma_fp64_fallback_sources": inf["n_sigma_fp64_fallback"],
-            "path": ["global", "lds", "batched", "narrow"][inf["path"]], "tuning": tune,
+            "path": PATH_NAME[inf["path"]], "tuning": tune,
             "batch_entries": inf["batch_entries"], "batch_edge_visits": inf["batch_edge_visits"],
             "batch_scans": inf["batch_scans"], "batch_handoffs": inf["batch_handoffs"],
             "batch_cycles_fwd_bwd_reset": inf["batch_cycles"],

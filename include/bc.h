@@ -72,8 +72,11 @@ typedef struct {
     int32_t use_graph;          /* 1 = replay a captured hipGraph, -1 = plain launches */
     int32_t batched;            /* 1 = 64 sources per batch (one per wavefront lane),
                                    -1 = one source per workgroup,
-                                   2 = one source per workgroup with each level held in LDS
-                                       (switched off: BC_E_INVAL) */
+                                   3 = one source per workgroup with each BFS level held in
+                                       LDS hash tables (deep graphs: lattices, meshes);
+                                       switched off (BC_E_INVAL) until a device fault of its
+                                       first run is explained,
+                                   2 = an earlier levels-in-LDS kernel, removed: BC_E_INVAL */
     int32_t batch_wg_size;      /* workgroup size of the batched kernel: 256, 512, 1024 */
     int32_t batch_pull;         /* batched kernel, direction of the forward sweep: a level is
                                    built from the unreached vertices' in-edges (pulled) instead
@@ -89,8 +92,10 @@ typedef struct {
     uint32_t path;                  /* 0 = one source per workgroup, state in global memory;
                                        1 = one source per workgroup, state in LDS;
                                        2 = 64-source batches;
-                                       3 = one source per workgroup, levels in LDS;
-                                       4, 5, 6 = bc_paper_strategy 1, 2, 3 */
+                                       3 = (removed) an earlier levels-in-LDS kernel;
+                                       4, 5, 6 = bc_paper_strategy 1, 2, 3;
+                                       7 = one source per workgroup, levels in LDS tables
+                                           (sources handed on counted in batch_handoffs) */
     double kernel_ms;               /* device time of the call (HIP events) */
     double t_submit_ms, t_start_ms, t_done_ms; /* bc_serve_poll only: server clock */
     uint64_t reached;               /* sum over sources of vertices reached (source included) */
@@ -99,9 +104,9 @@ typedef struct {
     uint64_t batch_entries;         /* path 2: (vertex, level) entries of the batches' lists */
     uint64_t batch_edge_visits;     /* path 2: out-edges of those entries */
     uint64_t batch_scans;           /* path 2: level-collect passes (each reads every vertex's masks) */
-    uint64_t batch_handoffs;        /* paths 2, 3: sources handed to the one-source-per-workgroup
+    uint64_t batch_handoffs;        /* paths 2, 7: sources handed to the one-source-per-workgroup
                                        kernel with state in global memory (path 2: 32-bit count cap,
-                                       list capacity or level cap; path 3: a level wider than the
+                                       list capacity or level cap; path 7: a level wider than the
                                        LDS tables) */
     uint64_t batch_cycles[3];       /* path 2: workgroup clock cycles summed over workgroups, in the
                                        forward sweep, the backward sweep, and state reset */

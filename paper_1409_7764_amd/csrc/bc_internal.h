@@ -61,7 +61,7 @@ struct CallStats {
     uint32_t bad_source;     // sources with id >= n (skipped)
     uint32_t work_head2;     // work counter of a follow-up launch in the same call
     uint32_t aborted;        // a batched team gave up waiting at a barrier
-    uint32_t handoffs;       // batched and narrow paths: sources handed to the global-memory kernel
+    uint32_t handoffs;       // batched and deep-graph paths: sources handed to the global-memory kernel
     uint64_t reached;        // sum over sources of reached vertices (source included)
     uint64_t examined;       // sum over sources of out-edges of reached vertices
     uint64_t dag_edges;      // sum over sources of shortest-path DAG edges
@@ -83,8 +83,8 @@ struct Knobs {
     int hub = 32;                // wavefront-per-vertex threshold
     int lds_max_n = 4096;
     bool use_graph = true;
-    int batched = 0;             // 1: 64-source batches, -1: one source per workgroup, 2: one source per
-                                 // workgroup with its levels in LDS, 0: auto
+    int batched = 0;             // 1: 64-source batches, -1: one source per workgroup, 3: one source per
+                                 // workgroup with its levels in LDS tables, 0: auto (2: rejected)
     int batch_wg = 1024;         // workgroup size of the batched kernel
     int batch_pull = 32;         // batched path: pull a level when (in-edges of unreached vertices) * 16 <
                                  // (out-edges of the level) * batch_pull; <= 0 = never
@@ -246,15 +246,17 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
                      int wg, int team_knob, int slots_cap, int pull16, hipStream_t st, RetryLaunch retry_launch,
                      void* retry_ctx);
 
-// ---- one source per workgroup, levels in LDS (narrow.hip) ---------------------------------
-struct NarrowPool;
-NarrowPool* narrow_pool_new();
-void narrow_pool_delete(NarrowPool* p);
-size_t narrow_slot_bytes(uint32_t n);
+// ---- one source per workgroup, levels in LDS hash tables (deep.hip) ----------------------
+struct DeepPool;
+DeepPool* deep_pool_new();
+void deep_pool_delete(DeepPool* p);
+size_t deep_slot_bytes(uint32_t n);
+void deep_geometry(int device, uint32_t& H, uint32_t& F, size_t& dyn);
 // sources given in caller numbering (null: item i is source i); sources whose levels outgrow
 // the LDS tables are handed to `retry_launch` with caller ids
-void run_narrow_enqueue(NarrowPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc,
-                        CallStats* stats, int slots_cap, hipStream_t st, RetryLaunch retry_launch, void* retry_ctx);
+void run_deep_enqueue(DeepPool& p, const Graph& g, const uint32_t* sources, uint32_t k, double* bc,
+                      uint8_t* ovf_flags, CallStats* stats, int slots_cap, hipStream_t st, RetryLaunch retry_launch,
+                      void* retry_ctx);
 
 // ---- the paper's three strategies as baselines (strategies.hip) ---------------------------
 void strat_pool_delete(StratPool* p);

@@ -947,7 +947,7 @@ struct GraphScratch {
     WorkDesc* desc = nullptr;    // device, one descriptor
     WorkDesc* rdesc = nullptr;   // device, descriptor of the retry list
     MsbPool* msb = nullptr;
-    NarrowPool* narrow = nullptr;
+    DeepPool* deep = nullptr;
 };
 
 static GraphScratch& scratch_of(Graph& g) {
@@ -962,7 +962,7 @@ void graph_scratch_free(Graph& g) {
     if (s->desc) (void)hipFree(s->desc);
     if (s->rdesc) (void)hipFree(s->rdesc);
     msb_pool_delete(s->msb);
-    narrow_pool_delete(s->narrow);
+    deep_pool_delete(s->deep);
     delete s;
     g.slots = nullptr;
 }
@@ -1022,24 +1022,27 @@ static void retry_launch(void* ctx, const uint32_t* list, const uint32_t* count,
 }
 
 int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g);
-int run_narrow(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g);
+int run_deep(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g);
 
 // Automatic choice: the batched kernel for graphs beyond the LDS path with at least one full
 // batch of sources, unless the graph is deep (most of it lies beyond the batching order's
 // ranked levels): a batch then runs past the kernel's level cap and goes to the per-source
 // kernel anyway.
 static bool want_batched(const Knobs& k, const Graph& g, uint32_t items) {
-    if (k.batched < 0 || k.batched == 2) return false;
+    if (k.batched < 0 || k.batched >= 2) return false;
     const bool lds_ok = k.lds_max_n > 0 && g.n <= k.lds_max_n;
     if (k.batched > 0) return true;
     return !lds_ok && items >= 64 && !g.deep;
 }
 
-// The levels-in-LDS kernel (narrow.hip) is switched off: its first device run faulted and the
-// cause is not yet known.  Asking for it is an error; deep graphs keep the global-memory
-// kernel.
-static bool want_narrow(const Knobs& k, const Graph&) {
-    BC_REQUIRE(k.batched != 2, BC_E_INVAL, "the levels-in-LDS path (batched = 2) is switched off");
+// One source per workgroup with its levels in LDS tables (deep.hip).  Switched off: its first
+// device run ended in an illegal memory access whose cause has not been shown (a host
+// emulation of the same source, under address and thread sanitizers, matches the oracle on
+// the same inputs).  The value 2 named an earlier kernel of that kind, removed after a device
+// fault.  Asking for either is an error; deep graphs run the global-memory kernel.
+static bool want_deep(const Knobs& k, const Graph&) {
+    BC_REQUIRE(k.batched != 2, BC_E_INVAL, "batched = 2 (an earlier levels-in-LDS kernel) was removed");
+    BC_REQUIRE(k.batched != 3, BC_E_INVAL, "the deep-graph path (batched = 3) is switched off");
     return false;
 }
 
@@ -1088,7 +1091,7 @@ void reset_slot_records(VRec* rec, size_t count, hipStream_t st) {
 int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     GraphScratch& gs = scratch_of(g);
     const bool exporting = ra.ex_dist || ra.ex_sigma || ra.ex_sigma_f || ra.ex_delta;
-    if (!exporting && want_narrow(k, g)) return run_narrow(ra, k, st, g);
+    if (!exporting && want_deep(k, g)) return run_deep(ra, k, st, g);
     if (!exporting && want_batched(k, g, ra.num_items)) return run_batched(ra, k, st, g);
     if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
     if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
@@ -1147,18 +1150,22 @@ int run_batched(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     return 2;
 }
 
-int run_narrow(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
+int run_deep(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     GraphScratch& gs = scratch_of(g);
     if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
     if (!gs.rdesc) BC_HIP_TRY(hipMalloc((void**)&gs.rdesc, sizeof(WorkDesc)));
     if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
-    if (!gs.narrow) gs.narrow = narrow_pool_new();
+    if (!gs.deep) gs.deep = deep_pool_new();
     WorkDesc d{};
+    d.row_ptr = g.row_ptr;
+    d.col = g.col;
     d.bc = ra.bc;
+    d.ovf_flags = ra.ovf_flags;
     d.n = g.n;
+    d.max_in = g.max_in_degree;
     d.num_items = ra.num_items;
     BC_HIP_TRY(hipMemcpyAsync(gs.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
-    // zero BC and the call counters
+    // zero BC, the flags and the call counters
     LaunchPlan z;
     z.args.descs = gs.desc;
     z.args.ndesc = 1;
@@ -1168,8 +1175,9 @@ int run_narrow(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     z.grid = 0;
     enqueue_plan(z, st, (uint32_t)g.n);
     RetryCtx rc{&g, &gs, k, ra.bc, ra.ovf_flags};
-    run_narrow_enqueue(*gs.narrow, g, ra.sources, ra.num_items, ra.bc, g.stats, k.teams, st, retry_launch, &rc);
-    return 3;
+    run_deep_enqueue(*gs.deep, g, ra.sources, ra.num_items, ra.bc, ra.ovf_flags, g.stats, k.teams, st, retry_launch,
+                     &rc);
+    return 7;
 }
 
 // Drops the batched path's state after a team gave up on a barrier (the state is dirty).

@@ -121,7 +121,7 @@ Knobs resolve_knobs(Graph& g, const bc_tuning* t) {
     if (t->lds_max_n) k.lds_max_n = t->lds_max_n;
     if (t->use_graph) k.use_graph = t->use_graph > 0;
     if (t->batched) {
-        BC_REQUIRE(t->batched >= -1 && t->batched <= 2, BC_E_INVAL, "batched must be -1, 0, 1 or 2");
+        BC_REQUIRE(t->batched >= -1 && t->batched <= 3, BC_E_INVAL, "batched must be -1, 0, 1, 2 or 3");
         k.batched = t->batched;
     }
     if (t->batch_pull) k.batch_pull = t->batch_pull;

@@ -132,7 +132,7 @@ PATHS = {
     "global": dict(lds_max_n=-1, batched=-1),
     "batched": dict(lds_max_n=-1, batched=1),
 }
-PATH_CODE = {"lds": 1, "global": 0, "batched": 2, "narrow": 3}
+PATH_CODE = {"lds": 1, "global": 0, "batched": 2, "narrow": 3, "deep": 7}
 
 
 def force(bc, path, **kw):
@@ -427,8 +427,9 @@ def lattice_with_hubs(rows, cols, hubs, fan, seed):
     return n, np.concatenate([u, hu]), np.concatenate([v, hv])
 
 
-NARROW_OFF = ("the levels-in-LDS kernel is switched off: its first device run faulted with an illegal "
-              "memory access and the cause has not been shown")
+NARROW_OFF = ("an earlier levels-in-LDS kernel (batched = 2) was removed: its first device run faulted with "
+              "an illegal memory access and the cause was not shown; the deep-graph path (batched = 3) is "
+              "a new kernel, tested below")
 
 
 @pytest.mark.skip(reason=NARROW_OFF)
@@ -474,6 +475,73 @@ def test_narrow_is_automatic_for_deep_graphs(bc):
     g.free()
 
 
+DEEP = dict(lds_max_n=-1, batched=3)
+DEEP_OFF = ("the deep-graph kernel (batched = 3) is switched off: its first device run (the lattice case "
+            "below) ended in an illegal memory access whose cause has not been shown")
+
+
+@pytest.mark.skip(reason=DEEP_OFF)
+@pytest.mark.parametrize("case", ["lattice", "hubs", "wide", "diamond", "griddag", "path", "rmat"])
+def test_deep_levels(bc, case):
+    """The levels-in-LDS-tables path against the oracle: BC, work counters, depth and the
+    overflow set, on sources that stay in the tables, that go on in double precision (diamond
+    chain, grid DAG) and that outgrow them (star, R-MAT: handed to the global-memory kernel);
+    with every resident slot, and with three slots each running ~100 sources in turn."""
+    if case == "lattice":
+        n, u, v = gg.grid_random_orientation(90, 70, 3)
+    elif case == "hubs":
+        n, u, v = lattice_with_hubs(60, 60, 12, 70, 4)
+    elif case == "wide":   # a bidirectional star: every level past the centre holds all leaves
+        n, u, v = gg.bidirectional_star(3000)
+    elif case == "diamond":
+        n, u, v = gg.diamond_chain(80)
+    elif case == "griddag":
+        n, u, v = gg.grid_dag(35, 35)
+    elif case == "path":
+        n, u, v = gg.directed_path(3000)
+    else:
+        n, u, v = gg.rmat(12, 8, 12)
+    o = oracle.Graph(n, u, v)
+    S = np.concatenate([gg.uniform_sources(n, min(n, 300), 9), np.zeros(2, np.uint32)])
+    want, ovf, st = oracle.bc(o, S)
+    g = bc.bc_build_csr(n, u, v)
+    for kw in [{}, dict(sources_per_launch=3)]:
+        say("deep", case, kw)
+        got, flags, info = bc.bc_sampled_flags(g, S, tuning=bc.tuning(**DEEP, **kw), info=True)
+        assert info["path"] == 7 and info["n_sources"] == len(S)
+        assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+        assert info["levels_max"] == int(st[:, 3].max())
+        assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
+        check_overflow_set(flags, S, ovf, n)
+        if case == "wide":
+            assert info["batch_handoffs"] == len(S)   # every source outgrows the tables
+        elif case in ("lattice", "path", "diamond", "griddag"):
+            assert info["batch_handoffs"] == 0
+        rel_close(np_of(got), want, what=f"deep {case}")
+    g.free()
+
+
+@pytest.mark.skip(reason=DEEP_OFF)
+def test_deep_exact_and_empty(bc):
+    """Exact BC on the path (every vertex a source), sources out of range, and a graph with no
+    edges."""
+    n, u, v = gg.grid_random_orientation(33, 31, 6)
+    want, ovf, _ = oracle.bc(oracle.Graph(n, u, v))
+    g = bc.bc_build_csr(n, u, v)
+    say("deep exact lattice 33x31")
+    got, info = bc.bc_exact(g, tuning=bc.tuning(**DEEP), info=True)
+    assert info["path"] == 7 and info["n_sources"] == n and info["n_sigma_fp64_fallback"] == int(ovf.sum())
+    rel_close(np_of(got), want)
+    with pytest.raises(bc.BcError) as e:
+        bc.bc_sampled(g, np.array([0, n], np.uint32), tuning=bc.tuning(**DEEP))
+    assert e.value.code == bc.BC_E_RANGE
+    g.free()
+    g = bc.bc_build_csr(50, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    got, info = bc.bc_exact(g, tuning=bc.tuning(**DEEP), info=True)
+    assert info["path"] == 7 and info["reached"] == 50 and not np_of(got).any()
+    g.free()
+
+
 def test_deep_graph_caller_numbering(bc):
     """A deep graph above the relabelling size runs the global-memory kernel on the caller's
     own numbering (the automatic choice); results and work counters match the oracle."""
@@ -498,9 +566,10 @@ def test_deep_graph_caller_numbering(bc):
 def test_narrow_request_is_rejected(bc):
     n, u, v = gg.grid_random_orientation(20, 20, 5)
     g = bc.bc_build_csr(n, u, v)
-    with pytest.raises(bc.BcError) as e:
-        bc.bc_exact(g, tuning=bc.tuning(lds_max_n=-1, batched=2))
-    assert e.value.code == bc.BC_E_INVAL
+    for batched in (2, 3):   # the removed kernel, and the deep-graph kernel while switched off
+        with pytest.raises(bc.BcError) as e:
+            bc.bc_exact(g, tuning=bc.tuning(lds_max_n=-1, batched=batched))
+        assert e.value.code == bc.BC_E_INVAL
     g.free()
 
 
