@@ -513,12 +513,14 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
     uint32_t W = a.team_size ? a.team_size : max(1u, min(32u, gridDim.x / want));
     W = min(W, gridDim.x);
     const uint32_t per_xcd = gridDim.x / 8;
-    const bool xcd = gridDim.x % 8 == 0 && per_xcd % W == 0;
     uint32_t team, member;
-    if (xcd) {
-        const uint32_t x = blockIdx.x % 8, l = blockIdx.x / 8;
-        team = x * (per_xcd / W) + l / W;
-        member = l % W;
+    if (gridDim.x % 8 == 0) {
+        // XCD-major numbering: a team takes consecutive workgroups of one XCD and spills into
+        // the next only when W does not divide the per-XCD count (a team of 28 out of 32 per
+        // XCD spans at most two L2s instead of all eight)
+        const uint32_t lin = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+        team = lin / W;
+        member = lin % W;
     } else {
         team = blockIdx.x / W;
         member = blockIdx.x % W;
