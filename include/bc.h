@@ -83,6 +83,15 @@ typedef struct {
                                    of its entries' out-edges when (in-edges of vertices some
                                    source has not reached) * 16 < (out-edges of the level's
                                    entries) * batch_pull; < 0 = always pushed (0 = automatic: 32) */
+    int32_t deterministic;      /* 1 = fixed summation order, for debugging: the one-source-per-
+                                   workgroup kernel with state in global memory, each workgroup
+                                   taking a static share of the sources in order, each vertex's
+                                   successor sum in CSR order, and BC reduced from per-workgroup
+                                   partial arrays (grid x n doubles) in workgroup order.  Two calls
+                                   with the same inputs and knobs then return the same bits, except
+                                   for sources whose counts pass 2^64 (their double-precision counts
+                                   are summed in arrival order).  Single-graph calls only; slower.
+                                   0 or < 0 = off */
 } bc_tuning;
 
 typedef struct {

@@ -33,7 +33,8 @@ class bc_tuning(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("wgs_per_source", ctypes.c_int32),
                 ("sources_per_launch", ctypes.c_int32), ("hub_threshold", ctypes.c_int32),
                 ("lds_max_n", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("batched", ctypes.c_int32),
-                ("batch_wg_size", ctypes.c_int32), ("batch_pull", ctypes.c_int32)]
+                ("batch_wg_size", ctypes.c_int32), ("batch_pull", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32)]
 
 
 class bc_info(ctypes.Structure):

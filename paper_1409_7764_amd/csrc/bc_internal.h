@@ -88,6 +88,7 @@ struct Knobs {
     int batch_wg = 1024;         // workgroup size of the batched kernel
     int batch_pull = 32;         // batched path: pull a level when (in-edges of unreached vertices) * 16 <
                                  // (out-edges of the level) * batch_pull; <= 0 = never
+    bool deterministic = false;  // fixed summation order (global-memory kernel, per-workgroup partials)
 };
 
 // Graph handle (the opaque bc_graph).
@@ -203,6 +204,11 @@ struct LaunchArgs {
     uint64_t* ex_sigma;
     double* ex_sigma_f;
     double* ex_delta;
+    // deterministic mode (global-memory kernel): workgroup b takes items b, b + grid, ... in
+    // order and adds its dependencies into part + b * n (plain adds); a fixed-order reduction
+    // over the workgroups writes BC
+    double* part;
+    uint32_t det;
 };
 
 // Device-resident per-source state slots of the global-memory path.

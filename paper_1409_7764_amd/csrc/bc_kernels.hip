@@ -452,7 +452,7 @@ template <bool F64, int WG, class S>
 __device__ void accumulate_level(S& st, Scratch<WG>& L, const uint32_t* __restrict__ row_ptr,
                                  const uint32_t* __restrict__ col, uint32_t lo, uint32_t hi, int d, uint32_t hub,
                                  uint32_t tpv_max, uint32_t src, double* __restrict__ bc, double* ex_delta,
-                                 const uint32_t* __restrict__ iperm) {
+                                 const uint32_t* __restrict__ iperm, double* part) {
     const unsigned tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
     constexpr unsigned NW = WG / 64;
     const int d1 = d + 1;
@@ -467,10 +467,25 @@ __device__ void accumulate_level(S& st, Scratch<WG>& L, const uint32_t* __restri
             deg = row_ptr[v + 1] - beg;
             sv = st.val(v);
         }
+        double own = 0.0;
+        if (part) {
+            // deterministic mode: thread per vertex over all of its successors, summed in CSR
+            // order (kIlp loads in flight, no atomics)
+            for (uint32_t e0 = 0; e0 < deg; e0 += kIlp) {
+                uint32_t w[kIlp];
+#pragma unroll
+                for (int t = 0; t < kIlp; ++t) w[t] = col[beg + min(e0 + (uint32_t)t, deg - 1)];
+                double c[kIlp];
+#pragma unroll
+                for (int t = 0; t < kIlp; ++t) c[t] = st.psi_if_level(w[t], d1);
+#pragma unroll
+                for (int t = 0; t < kIlp; ++t)
+                    if (e0 + (uint32_t)t < deg) own += c[t];
+            }
+        } else {
         const bool is_hub = valid && deg >= hub;
         uint32_t so, stot, po, ptot, mx;
         classify_chunk<WG>(L, deg, is_hub, so, stot, po, ptot, mx);
-        double own = 0.0;
         if (ptot == 0 && mx <= tpv_max) {
             // thread per vertex, at most kTpv successors: every successor id, then every
             // successor record, is loaded before the first is used (two round trips, not two per
@@ -537,12 +552,18 @@ __device__ void accumulate_level(S& st, Scratch<WG>& L, const uint32_t* __restri
             __syncthreads();
             own = L.acc[tid];
         }
+        }
         if (valid) {
             const double sigma = F64 ? u2d(sv) : (double)sv;
             const double delta = sigma * own;
             st.set_val(v, d2u((1.0 + delta) / sigma));
             const uint32_t out = iperm ? iperm[v] : v;
-            if (v != src && delta != 0.0) unsafeAtomicAdd(&bc[out], delta);
+            if (v != src && delta != 0.0) {
+                if (part)
+                    part[out] += delta;   // this workgroup's own array, one owner per vertex and source
+                else
+                    unsafeAtomicAdd(&bc[out], delta);
+            }
             if (ex_delta) ex_delta[out] = delta;
         }
         __syncthreads();
@@ -553,6 +574,7 @@ __device__ void accumulate_level(S& st, Scratch<WG>& L, const uint32_t* __restri
 template <int WG, class S>
 __device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s, const LaunchArgs& a) {
     const unsigned tid = threadIdx.x;
+    double* part = a.part ? a.part + (size_t)blockIdx.x * (size_t)D.n : nullptr;   // deterministic mode
     bool f64 = false;
     uint32_t count = 0;
     int nlev = 0;
@@ -629,10 +651,10 @@ __device__ void one_source(S& st, Scratch<WG>& L, const WorkDesc& D, uint32_t s,
         lo = st.level_begin(dd, hi);
         if (f64)
             accumulate_level<true, WG>(st, L, D.row_ptr, D.col, lo, hi, dd, a.hub, a.tpv_max, s, D.bc, a.ex_delta,
-                                       D.iperm);
+                                       D.iperm, part);
         else
             accumulate_level<false, WG>(st, L, D.row_ptr, D.col, lo, hi, dd, a.hub, a.tpv_max, s, D.bc, a.ex_delta,
-                                        D.iperm);
+                                        D.iperm, part);
         st.barrier();
         hi = lo;
     }
@@ -682,12 +704,13 @@ __device__ __forceinline__ uint32_t find_desc(const WorkDesc* descs, uint32_t nd
 // claims the next work item for the whole workgroup; false when the list is exhausted
 template <int WG>
 __device__ __forceinline__ bool claim_item(const LaunchArgs& a, Scratch<WG>& L, uint32_t& di, uint32_t& s,
-                                           uint32_t n_cap) {
+                                           uint32_t n_cap, uint32_t& seq) {
     const uint32_t total = a.items_dev ? *a.items_dev : a.total_items;
     uint32_t* head = a.head ? a.head : &a.stats->work_head;
     for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t item = atomicAdd(head, 1u);
+            // deterministic mode: a static share, in order (thread 0 keeps the sequence)
+            const uint32_t item = a.det ? blockIdx.x + (seq++) * gridDim.x : atomicAdd(head, 1u);
             L.item = item;
             L.desc = item < total ? find_desc(a.descs, a.ndesc, item) : 0u;
         }
@@ -720,8 +743,8 @@ __global__ void __launch_bounds__(WG) k_bc_global(LaunchArgs a) {
     st.rec = a.rec + (size_t)blockIdx.x * a.slot_n;
     st.queue = a.queue + (size_t)blockIdx.x * a.slot_n;
     st.lvl = a.lvl + (size_t)blockIdx.x * ((size_t)a.slot_n + 1);
-    uint32_t di, s;
-    while (claim_item<WG>(a, L, di, s, a.slot_n)) one_source<WG>(st, L, a.descs[di], s, a);
+    uint32_t di, s, seq = 0;
+    while (claim_item<WG>(a, L, di, s, a.slot_n, seq)) one_source<WG>(st, L, a.descs[di], s, a);
 }
 
 template <int WG>
@@ -739,8 +762,8 @@ __global__ void __launch_bounds__(WG) k_bc_lds(LaunchArgs a) {
         st.dist16[i] = kUnseen16;
     }
     __syncthreads();
-    uint32_t di, s;
-    while (claim_item<WG>(a, L, di, s, cap)) one_source<WG>(st, L, a.descs[di], s, a);
+    uint32_t di, s, seq = 0;
+    while (claim_item<WG>(a, L, di, s, cap, seq)) one_source<WG>(st, L, a.descs[di], s, a);
 }
 
 __global__ void k_prepare(const WorkDesc* descs, uint32_t ndesc, CallStats* stats, uint32_t zero_outputs) {
@@ -1088,9 +1111,61 @@ void reset_slot_records(VRec* rec, size_t count, hipStream_t st) {
     BC_HIP_TRY(hipGetLastError());
 }
 
+namespace {
+// BC = the workgroups' partial arrays summed in workgroup order (deterministic mode)
+__global__ void k_reduce_parts(const double* __restrict__ part, uint32_t groups, uint32_t n, double* bc) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        double sum = 0.0;
+        for (uint32_t b = 0; b < groups; ++b) sum += part[(size_t)b * n + v];
+        bc[v] = sum;
+    }
+}
+}  // namespace
+
+// Deterministic mode: the global-memory kernel with a static share of the sources per
+// workgroup, successor sums in CSR order, and per-workgroup partial BC arrays (at most a
+// quarter of free device memory) reduced in workgroup order.
+static int run_deterministic(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
+    GraphScratch& gs = scratch_of(g);
+    if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));
+    if (!g.stats) BC_HIP_TRY(hipMalloc((void**)&g.stats, sizeof(CallStats)));
+    const uint32_t n = (uint32_t)g.n;
+    const WorkDesc d = single_graph_desc(g, ra);
+    BC_HIP_TRY(hipMemcpyAsync(gs.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    Knobs kd = k;
+    kd.lds_max_n = -1;   // state in global memory
+    LaunchPlan p = make_plan(kd, n, ra.num_items, g.device);
+    size_t free_b = 0, total_b = 0;
+    BC_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const size_t per = (size_t)n * sizeof(double);
+    const size_t fit = std::max<size_t>(1, (free_b / 4) / per);
+    p.grid = (unsigned)std::min<size_t>(p.grid, fit);
+    pool_ensure(gs.pool, n, (int)p.grid, st);
+    p.args.rec = gs.pool.rec;
+    p.args.queue = gs.pool.queue;
+    p.args.lvl = gs.pool.lvl;
+    p.args.slot_n = gs.pool.slot_n;
+    p.args.descs = gs.desc;
+    p.args.ndesc = 1;
+    p.args.total_items = ra.num_items;
+    p.args.stats = g.stats;
+    double* part = nullptr;
+    BC_HIP_TRY(hipMallocAsync((void**)&part, (size_t)p.grid * per, st));
+    BC_HIP_TRY(hipMemsetAsync(part, 0, (size_t)p.grid * per, st));
+    p.args.part = part;
+    p.args.det = 1;
+    enqueue_plan(p, st, n);   // zeroes BC and the counters, then the search
+    hipLaunchKernelGGL(k_reduce_parts, dim3(std::max(1u, std::min<unsigned>((n + 255) / 256, 4096))), dim3(256), 0,
+                       st, part, p.grid, n, ra.bc);
+    BC_HIP_TRY(hipGetLastError());
+    BC_HIP_TRY(hipFreeAsync(part, st));
+    return 0;
+}
+
 int run_sources(const RunArgs& ra, const Knobs& k, hipStream_t st, Graph& g) {
     GraphScratch& gs = scratch_of(g);
     const bool exporting = ra.ex_dist || ra.ex_sigma || ra.ex_sigma_f || ra.ex_delta;
+    if (!exporting && k.deterministic) return run_deterministic(ra, k, st, g);
     if (!exporting && want_deep(k, g)) return run_deep(ra, k, st, g);
     if (!exporting && want_batched(k, g, ra.num_items)) return run_batched(ra, k, st, g);
     if (!gs.desc) BC_HIP_TRY(hipMalloc((void**)&gs.desc, sizeof(WorkDesc)));

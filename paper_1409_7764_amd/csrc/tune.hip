@@ -125,6 +125,7 @@ Knobs resolve_knobs(Graph& g, const bc_tuning* t) {
         k.batched = t->batched;
     }
     if (t->batch_pull) k.batch_pull = t->batch_pull;
+    if (t->deterministic) k.deterministic = t->deterministic > 0;
     if (t->batch_wg_size) {
         BC_REQUIRE(t->batch_wg_size == 256 || t->batch_wg_size == 512 || t->batch_wg_size == 1024, BC_E_INVAL,
                    "batch_wg_size must be 256, 512 or 1024");

@@ -41,6 +41,31 @@ def test_library_exports_every_declared_symbol(libpath):
     assert lib.bc_last_error() == b""
 
 
+def struct_fields(name):
+    """Field names of a typedef struct in the public header, in order."""
+    text = open(HEADER).read()
+    end = re.search(r"\}\s*" + name + ";", text).start()
+    body = text[text.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        names = decl.split(",")   # "double a, b, c": the type goes with the first name
+        for part in names:
+            m = re.search(r"(\w+)\s*(\[\d+\])?\s*$", part.strip())
+            out.append(m.group(1))
+    return out
+
+
+@pytest.mark.parametrize("name", ["bc_tuning", "bc_info"])
+def test_binding_structs_match_the_header(name):
+    """The Python binding's ctypes structures list the header's fields in the header's order."""
+    from paper_1409_7764_amd import bcmi
+    assert [f for f, _ in getattr(bcmi, name)._fields_] == struct_fields(name)
+
+
 def test_library_holds_gfx950_code(libpath):
     data = open(libpath, "rb").read()
     assert b"gfx950" in data

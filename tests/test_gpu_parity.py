@@ -542,6 +542,45 @@ def test_deep_exact_and_empty(bc):
     g.free()
 
 
+@pytest.mark.parametrize("case", ["rmat12", "lattice", "diamond"])
+def test_deterministic_mode(bc, case):
+    """bc_tuning.deterministic: repeated calls return the same bits (with every resident
+    workgroup, and with seven), BC within 1e-9 of the oracle, exact zeros; the default path
+    agrees within the same tolerance.  The diamond chain's sources pass 2^64 (their counts go
+    on in double precision, each a sum of two terms, so their order cannot matter)."""
+    if case == "rmat12":
+        n, u, v = gg.rmat(12, 16, 3)
+        S = None
+    elif case == "lattice":
+        n, u, v = gg.grid_random_orientation(60, 60, 2)
+        S = gg.uniform_sources(n, 300, 4)
+    else:
+        n, u, v = gg.diamond_chain(80)
+        S = None
+    want, ovf, st = oracle.bc(oracle.Graph(n, u, v), S)
+    g = bc.bc_build_csr(n, u, v)
+
+    def call(t):
+        if S is None:
+            return bc.bc_exact(g, tuning=t, info=True)
+        return bc.bc_sampled(g, S, tuning=t, info=True)
+
+    for kw in [{}, dict(sources_per_launch=7)]:
+        say("deterministic", case, kw)
+        t = bc.tuning(deterministic=1, **kw)
+        runs = [call(t) for _ in range(3)]
+        for got, info in runs:
+            assert info["path"] == 0 and info["n_sources"] == (n if S is None else len(S))
+            assert info["n_sigma_fp64_fallback"] == int(ovf.sum())
+            assert (info["reached"], info["examined"], info["dag_edges"]) == tuple(int(x) for x in st[:, :3].sum(0))
+        bits = [np_of(r[0]).view(np.uint64) for r in runs]
+        assert np.array_equal(bits[0], bits[1]) and np.array_equal(bits[0], bits[2])
+        rel_close(np_of(runs[0][0]), want, what=f"deterministic {case} {kw}")
+    got, _ = call(None)
+    rel_close(np_of(got), want, what=f"default {case}")
+    g.free()
+
+
 def test_deep_graph_caller_numbering(bc):
     """A deep graph above the relabelling size runs the global-memory kernel on the caller's
     own numbering (the automatic choice); results and work counters match the oracle."""
