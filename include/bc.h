@@ -192,8 +192,8 @@ BC_API bc_status bc_sampled_noalloc(bc_graph g, const uint32_t* d_sources, int32
                                     const bc_tuning* t, void* stream);
 
 /* One source, for inspection (section I: the BFS distances d(s,.) and shortest-path counts
- * sigma(s,.) of the forward sweep, and the dependencies delta_s(.) of the backward sweep): distances and path counts exactly as the forward sweep
- * leaves them, and the dependencies of the backward sweep.  d_dist (int32 n),
+ * sigma(s,.) exactly as the forward sweep leaves them, and the dependencies delta_s(.) of the
+ * backward sweep).  d_dist (int32 n),
  * d_sigma_u64 (uint64 n; exact counts, all 0 when overflowed), d_sigma_f64 (double n;
  * counts as doubles, the double-precision recount when overflowed), d_delta (double n;
  * delta_s(v), delta_s(s) = reached-1).  Any of the four may be NULL.  *h_overflowed is set
@@ -207,7 +207,11 @@ BC_API bc_status bc_batch(const bc_graph* gs, int32_t num_graphs, double* const*
                    const bc_tuning* t, void* stream, bc_info* infos);
 
 /* Autotune the launch knobs for this graph (times candidate configurations on a sample of
- * sources; cached per device and graph class).  Synchronous. */
+ * sources; cached per device and graph class): workgroup size, hub threshold, state home,
+ * sources per launch, and for the batched kernel its workgroup size, workgroups per batch and
+ * pull threshold.  Section III-E's observation, that the best block size depends on the graph
+ * and is not simply the largest, is why these are searched rather than fixed.  Writes the
+ * chosen knobs to *out.  Synchronous.  Errors: BC_E_INVAL (null handle or out), BC_E_HIP. */
 BC_API bc_status bc_tune(bc_graph g, bc_tuning* out);
 
 /* Approximate BC from pivot sources (the sampling approximation cited in section I): k
