@@ -85,7 +85,7 @@ struct Knobs {
     bool use_graph = true;
     int batched = 0;             // 1: 64-source batches, -1: one source per workgroup, 3: one source per
                                  // workgroup with its levels in LDS tables, 0: auto (2: rejected)
-    int batch_wg = 1024;         // workgroup size of the batched kernel
+    int batch_wg = 512;          // workgroup size of the batched kernel
     int batch_pull = 32;         // batched path: pull a level when (in-edges of unreached vertices) * 16 <
                                  // (out-edges of the level) * batch_pull; <= 0 = never
     bool deterministic = false;  // fixed summation order (global-memory kernel, per-workgroup partials)

@@ -48,6 +48,7 @@
 #include "bc_internal.h"
 
 #include <algorithm>
+#include <atomic>
 
 namespace bcmi {
 
@@ -110,7 +111,10 @@ namespace {
 
 // A team gives up waiting at a barrier after MsbArgs::wait_ticks of the constant-rate wall clock
 // (set by the host from the graph's size: far above what any level of that graph takes).
-constexpr int kPsiLoads = 16;               // backward: psi loads issued back to back
+// backward: psi loads issued back to back (a 1024-thread workgroup runs four wavefronts per
+// SIMD and keeps 16 in flight; smaller ones run six, with registers for 8)
+template <int WG>
+constexpr int kPsiLoads = WG >= 1024 ? 16 : 8;
 
 __device__ __forceinline__ unsigned lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -498,21 +502,25 @@ __device__ __forceinline__ uint32_t claim_chunk(MsbLds<WG>& L, TeamCtl* c) {
     return ch;
 }
 
+// Workgroups of up to 512 threads are built for six wavefronts per SIMD (80 VGPRs; the
+// loop-invariant state pointers spill): three 512-thread workgroups fill a compute unit's LDS,
+// and the extra wavefronts hide more of the gather latency (R-MAT scale 20: 27.8 -> 26.1 ms)
 template <int WG>
-__global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(WG <= 512 ? 6 : 1)))
+k_msb(MsbArgs a) {
     __shared__ MsbLds<WG> L;
     const unsigned tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
     constexpr unsigned NW = WG / 64;
     const uint32_t total = *a.plan_count;
     const uint32_t nbatch = (total + 63) / 64;
     // Team size, chosen on the device from the batch count: the grid is split into at most
-    // min(batches, pool slots) teams.  With 8-way round-robin dispatch, workgroups b, b+8,
-    // b+16, ... share an XCD; when W divides that stride group, a team is W of them, so its
-    // batch state stays behind one L2.
+    // min(batches, pool slots) teams, each at most one XCD's share of the grid.  With 8-way
+    // round-robin dispatch, workgroups b, b+8, b+16, ... share an XCD; when W divides that
+    // stride group, a team is W of them, so its batch state stays behind one L2.
     const uint32_t want = max(1u, min(nbatch, a.pool_teams));
-    uint32_t W = a.team_size ? a.team_size : max(1u, min(32u, gridDim.x / want));
-    W = min(W, gridDim.x);
     const uint32_t per_xcd = gridDim.x / 8;
+    uint32_t W = a.team_size ? a.team_size : max(1u, min(max(per_xcd, 1u), gridDim.x / want));
+    W = min(W, gridDim.x);
     uint32_t team, member;
     if (gridDim.x % 8 == 0) {
         // XCD-major numbering: a team takes consecutive workgroups of one XCD and spills into
@@ -798,13 +806,13 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                         }
                         dagc += (uint32_t)__builtin_popcountll(sm);
                         // lane per source: sum psi over the unit's successors, taken from the
-                        // ballot kPsiLoads at a time so that as many loads are in flight
+                        // ballot kPsiLoads<WG> at a time so that as many loads are in flight
                         uint64_t rem = __ballot(sm != 0ull);
                         double acc = 0.0;
                         while (rem) {
-                            double x[kPsiLoads];
+                            double x[kPsiLoads<WG>];
 #pragma unroll
-                            for (int t = 0; t < kPsiLoads; ++t) {
+                            for (int t = 0; t < kPsiLoads<WG>; ++t) {
                                 x[t] = 0.0;
                                 if (rem) {
                                     const int k = __builtin_ctzll(rem);
@@ -815,7 +823,7 @@ __global__ void __launch_bounds__(WG) k_msb(MsbArgs a) {
                                 }
                             }
 #pragma unroll
-                            for (int t = 0; t < kPsiLoads; ++t) acc += x[t];
+                            for (int t = 0; t < kPsiLoads<WG>; ++t) acc += x[t];
                         }
                         if (hr < 0) {
                             finish_entry(sig, psi, bcp, c0 + j, vj, fj, acc, cnt_v, my_src, dj, L.ws[wave]);
@@ -1054,7 +1062,14 @@ struct MsbPool {
     uint32_t plan_cap = 0;
     uint32_t* small = nullptr;      // [80] plan_count, [81] retry_count
     uint32_t* bhist = nullptr;      // [kPlanBuckets + 1] plan histogram / cursors
+    int device = -1;                // where the arrays live, and their size in bytes
+    size_t bytes = 0;
 };
+
+// Bytes held by the batched pools of every graph handle, per device.  A handle keeps its pool
+// between calls, so without a shared bound many large handles would each take half of what
+// the others left.
+static std::atomic<size_t> g_pool_bytes[64];
 
 size_t msb_team_bytes(uint32_t n, uint32_t cap, uint32_t max_levels) {
     return sizeof(TeamCtl) + (size_t)n * (16 + 8 + 16 + 256 + 512) + 5 * kStaggerWords * 8 + (size_t)cap * 20 +
@@ -1065,6 +1080,7 @@ void msb_pool_free(MsbPool& p) {
     for (void* q : {(void*)p.ctl, (void*)p.masks, (void*)p.bnx, (void*)p.cur, (void*)p.sig, (void*)p.psi, (void*)p.bcp, (void*)p.lst_m, (void*)p.hacc,
                     (void*)p.lst_v, (void*)p.lvl, (void*)p.plan, (void*)p.retry, (void*)p.small, (void*)p.bhist})
         if (q) (void)hipFree(q);
+    if (p.device >= 0 && p.device < 64) g_pool_bytes[p.device] -= p.bytes;
     p = MsbPool{};
 }
 
@@ -1080,8 +1096,8 @@ void msb_pool_discard(MsbPool* p) {
     if (p) msb_pool_free(*p);
 }
 
-static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t cap, uint32_t max_levels,
-                            uint32_t hub_rows, uint32_t plan_cap, hipStream_t st) {
+static void msb_pool_ensure(MsbPool& p, int device, uint32_t n, int teams, int wgs, uint32_t cap,
+                            uint32_t max_levels, uint32_t hub_rows, uint32_t plan_cap, hipStream_t st) {
     // a pool built for a larger graph serves a smaller one: its arrays are all zero between
     // batches, and the kernel takes its strides from the pool
     if (p.masks && p.n >= n && p.teams >= teams && p.wgs >= wgs && p.cap >= cap && p.max_levels >= max_levels &&
@@ -1116,6 +1132,13 @@ static void msb_pool_ensure(MsbPool& p, uint32_t n, int teams, int wgs, uint32_t
     BC_HIP_TRY(hipMalloc((void**)&p.retry, (size_t)p.plan_cap * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.small, 128 * 4));
     BC_HIP_TRY(hipMalloc((void**)&p.bhist, (size_t)(kPlanBuckets + 1) * 4));
+    p.bytes = (size_t)teams * (sizeof(TeamCtl) + 8 * (p.mask_stride + p.bnx_stride + p.psi_stride) +
+                               16 * p.cur_stride + 4 * p.sig_stride + 20 * (size_t)cap + 4 * ((size_t)max_levels + 2)) +
+              (size_t)wgs * hub_rows * 512 + (size_t)p.plan_cap * 8 + 128 * 4 + (size_t)(kPlanBuckets + 1) * 4;
+    if (device >= 0 && device < 64) {
+        p.device = device;
+        g_pool_bytes[device] += p.bytes;
+    }
     const size_t words = (size_t)teams * p.mask_stride;
     const unsigned g1 = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u64, dim3(g1), dim3(256), 0, st, p.masks, words);
@@ -1148,23 +1171,29 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     BC_REQUIRE(per_cu >= 1, BC_E_HIP, "batched kernel does not fit on a compute unit");
     const long max_wgs = (long)per_cu * di.cus;
     // state slots: one per team; the kernel forms min(batches, slots) teams on the device.
-    // Unless the caller fixes the team size, a team has at least four workgroups: fewer
-    // batches in flight keep more of their state in the caches (R-MAT scale 16: 488 GTEPS
-    // with one workgroup per team, 582 with two, 591 with four).
-    const long wmin = team_knob > 0 ? team_knob : 4;
+    // Unless the caller fixes the team size, a team has at least 4,096 threads: fewer batches
+    // in flight keep more of their state in the caches (R-MAT scale 16, 1,024-thread
+    // workgroups: 488 GTEPS with one per team, 582 with two, 591 with four; 512-thread
+    // workgroups: 96.1, 93.4, 91.4, 94.3 ms with 16, 12, 8, 4 per team).
+    const long wmin = team_knob > 0 ? team_knob : std::max(4, 4096 / wg);
     long teams = std::min<long>(batches, std::max<long>(1, max_wgs / wmin));
     if (slots_cap > 0) teams = std::min<long>(teams, slots_cap);
     const uint32_t cap = (uint32_t)std::min<uint64_t>((uint64_t)n * 8 + 64, 0xffffffffull);
     const uint32_t max_levels = 1024;
-    // bound the pool by free device memory (keep half of it for everything else)
+    // bound the pool by free device memory (keep half of it for everything else), and the
+    // pools of all handles on the device together by half of its memory
     size_t free_b = 0, total_b = 0;
     BC_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     const size_t per_team = msb_team_bytes(n, cap, max_levels);
     const size_t have = p.n >= n ? (size_t)p.teams * msb_team_bytes(p.n, p.cap, p.max_levels) : 0;
-    const size_t budget = (free_b + have) / 2 - std::min<size_t>((free_b + have) / 2, (size_t)max_wgs * wg * 512);
+    const size_t mine = p.device == g.device ? p.bytes : 0;
+    const size_t held = g.device >= 0 && g.device < 64 ? g_pool_bytes[g.device].load() : 0;
+    const size_t others = held > mine ? held - mine : 0;
+    const size_t room = std::min((free_b + have) / 2, total_b / 2 > others ? total_b / 2 - others : 0);
+    const size_t budget = room - std::min<size_t>(room, (size_t)max_wgs * wg * 512);
     teams = (long)std::max<size_t>(1, std::min<size_t>(teams, budget / std::max<size_t>(per_team, 1)));
     const int grid = (int)max_wgs;
-    msb_pool_ensure(p, n, (int)teams, grid, cap, max_levels, (uint32_t)wg, std::max<uint32_t>(k, n), st);
+    msb_pool_ensure(p, g.device, n, (int)teams, grid, cap, max_levels, (uint32_t)wg, std::max<uint32_t>(k, n), st);
 
     uint32_t* plan_count = p.small + 80;
     uint32_t* retry_count = p.small + 81;

@@ -35,7 +35,7 @@ Knobs default_knobs(const Graph& g) {
     k.hub = lds ? 128 : 64;
     k.use_graph = true;
     k.batched = 0;
-    k.batch_wg = 1024;
+    k.batch_wg = 512;
     k.batch_pull = 32;
     return k;
 }
