@@ -1171,17 +1171,20 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     BC_REQUIRE(per_cu >= 1, BC_E_HIP, "batched kernel does not fit on a compute unit");
     const long max_wgs = (long)per_cu * di.cus;
     // state slots: one per team; the kernel forms min(batches, slots) teams on the device.
-    // Unless the caller fixes the team size, a team has at least 4,096 threads: fewer batches
-    // in flight keep more of their state in the caches (R-MAT scale 16, 1,024-thread
-    // workgroups: 488 GTEPS with one per team, 582 with two, 591 with four; 512-thread
-    // workgroups: 96.1, 93.4, 91.4, 94.3 ms with 16, 12, 8, 4 per team).
-    const long wmin = team_knob > 0 ? team_knob : std::max(4, 4096 / wg);
-    long teams = std::min<long>(batches, std::max<long>(1, max_wgs / wmin));
+    // Unless the caller fixes the team size, a team has at least 4,096 threads, and there are
+    // at most a quarter as many slots as compute units: fewer batches in flight keep more of
+    // their state in the caches (R-MAT scale 16, 1,024-thread workgroups: 488 GTEPS with one
+    // per team, 582 with two, 591 with four; 512-thread workgroups: 96.1, 93.4, 91.4, 94.3 ms
+    // with 16, 12, 8, 4 per team), and a slot of a scale-18 graph holds 250 MB, kept by the
+    // handle between calls.
+    const long slots_max = team_knob > 0 ? max_wgs / team_knob
+                                         : std::min<long>(max_wgs / std::max(4, 4096 / wg), di.cus / 4);
+    long teams = std::min<long>(batches, std::max<long>(1, slots_max));
     if (slots_cap > 0) teams = std::min<long>(teams, slots_cap);
     const uint32_t cap = (uint32_t)std::min<uint64_t>((uint64_t)n * 8 + 64, 0xffffffffull);
     const uint32_t max_levels = 1024;
     // bound the pool by free device memory (keep half of it for everything else), and the
-    // pools of all handles on the device together by half of its memory
+    // pools of all handles on the device together by three quarters of its memory
     size_t free_b = 0, total_b = 0;
     BC_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     const size_t per_team = msb_team_bytes(n, cap, max_levels);
@@ -1189,7 +1192,8 @@ void run_msb_enqueue(MsbPool& p, const Graph& g, const uint32_t* sources, uint32
     const size_t mine = p.device == g.device ? p.bytes : 0;
     const size_t held = g.device >= 0 && g.device < 64 ? g_pool_bytes[g.device].load() : 0;
     const size_t others = held > mine ? held - mine : 0;
-    const size_t room = std::min((free_b + have) / 2, total_b / 2 > others ? total_b / 2 - others : 0);
+    const size_t all = total_b / 4 * 3;
+    const size_t room = std::min((free_b + have) / 2, all > others ? all - others : 0);
     const size_t budget = room - std::min<size_t>(room, (size_t)max_wgs * wg * 512);
     teams = (long)std::max<size_t>(1, std::min<size_t>(teams, budget / std::max<size_t>(per_team, 1)));
     const int grid = (int)max_wgs;
