@@ -64,7 +64,10 @@ typedef struct bc_server_s* bc_server;
  * or built-in defaults when tuning is switched off with BCMI_TUNE=off). */
 typedef struct {
     int32_t wg_size;            /* threads per workgroup, multiple of 64 in [64, 1024] */
-    int32_t wgs_per_source;     /* workgroups cooperating on one source (1, 2, 4, 8) */
+    int32_t wgs_per_source;     /* workgroups cooperating on one source (1, 2, 4, 8), or on one
+                                   64-source batch of the batched kernel (1..64; 0 = automatic:
+                                   the grid split over min(batches, compute units / 4) batches,
+                                   at most one XCD's share each) */
     int32_t sources_per_launch; /* concurrent sources (per-source state slots) */
     int32_t hub_threshold;      /* out-degree from which a vertex is expanded by a whole
                                    wavefront rather than one thread; < 0 = never */
@@ -77,7 +80,8 @@ typedef struct {
                                        switched off (BC_E_INVAL) until a device fault of its
                                        first run is explained,
                                    2 = an earlier levels-in-LDS kernel, removed: BC_E_INVAL */
-    int32_t batch_wg_size;      /* workgroup size of the batched kernel: 256, 512, 1024 */
+    int32_t batch_wg_size;      /* workgroup size of the batched kernel: 256, 512, 1024
+                                   (0 = automatic: 512, three per compute unit) */
     int32_t batch_pull;         /* batched kernel, direction of the forward sweep: a level is
                                    built from the unreached vertices' in-edges (pulled) instead
                                    of its entries' out-edges when (in-edges of vertices some
